@@ -1,0 +1,241 @@
+"""Plain CSR statement of the stage preconditioners and the multigrid V-cycle (FP64, CPU).
+
+Test infrastructure only (see the package docstring).
+
+Section 3.1 (Block preconditioners) splits the Butcher matrix A = L + D + U and
+replaces A by D (block Jacobi, eq:pcbjac) or by L + D (block Gauss-Seidel,
+eq:pcbgs). The paper states both for the form eq:block_struct_IA and notes that
+the form eq:block_struct_AI "follows similarly"; the reading used here (the AI
+form) is
+
+    P_D = I (x) M + dt * D (x) K,         P_L = I (x) M + dt * (L + D) (x) K.
+
+Applying P_L^{-1} to v is block forward substitution:
+    t_i = v_i - dt * K * sum_{j<i} a_ij z_j,    z_i = B_i^{-1} t_i,
+with the diagonal blocks B_i = M + dt * a_ii * K (the backward-Euler-like blocks
+of Section 3.1, there written a_jj^{-1} M + dt K for the IA form). The paper
+approximates B_i^{-1} by multigrid; this module states the geometric multigrid
+V-cycle used for that:
+
+  * levels N, N/2, ... while the element count stays even and the next level has
+    at least `coarse_n` elements per side; the coarse problem is rediscretised
+    with the per-element diffusivity averaged over the 4 children;
+  * prolongation P = bilinear interpolation, restriction = P^T;
+  * smoother: Chebyshev iteration of a given degree preconditioned by point
+    Jacobi (for Q1 the vertex-patch additive Schwarz smoother of Section 3.2
+    reduces to point Jacobi), on the interval [lo*mu, hi*mu] with mu the
+    largest eigenvalue of D^{-1}B estimated by power iteration (the paper's
+    relaxation uses [0.25 mu, 1.1 mu] with mu estimated, Section 4.3);
+  * coarsest level: a direct solve (the paper uses a direct method on the
+    coarsest grid, Section 4.3).
+
+Power iteration start vectors come from the SplitMix64 generator (Steele, Lea &
+Flood, OOPSLA 2014), written here from its published definition; the GPU library
+carries its own implementation.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import fem
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(z: int) -> int:
+    """One output of SplitMix64 for the counter value z (Steele, Lea & Flood 2014)."""
+    z = (z + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def start_vector(n: int, level: int) -> np.ndarray:
+    """Power-iteration start vector: entry p is 2*U - 1, U = top 53 bits of splitmix64(p + level*2^32) / 2^53.
+
+    Vectorised with wrapping uint64 arithmetic; :func:`splitmix64` is the scalar statement.
+    """
+    z = np.arange(n, dtype=np.uint64) + np.uint64(level << 32)
+    with np.errstate(over="ignore"):
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return 2.0 * ((z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)) - 1.0
+
+
+def level_sizes(N: int, coarse_n: int = 8):
+    """Element counts per side of the multigrid levels, finest first."""
+    sizes = [N]
+    while sizes[-1] % 2 == 0 and sizes[-1] // 2 >= coarse_n:
+        sizes.append(sizes[-1] // 2)
+    return sizes
+
+
+def coarsen_kappa(N: int, kappa: np.ndarray) -> np.ndarray:
+    """Per-element diffusivity of the next level: the mean of the 4 children."""
+    k = np.asarray(kappa).reshape(N, N)
+    kc = 0.25 * (k[0::2, 0::2] + k[0::2, 1::2] + k[1::2, 0::2] + k[1::2, 1::2])
+    return kc.ravel()
+
+
+def prolongation(Nc: int) -> sp.csr_matrix:
+    """Bilinear interpolation from the interior nodes of an Nc grid to those of the 2*Nc grid.
+
+    Fine node (i, j) receives w(i - 2I) w(j - 2J) of coarse node (I, J), with
+    w(0) = 1, w(+-1) = 1/2. Coarse boundary nodes carry zero.
+    """
+    Nf = 2 * Nc
+    fidx = fem.interior_index(Nf)
+    cidx = fem.interior_index(Nc)
+    rows, cols, vals = [], [], []
+    w = {0: 1.0, 1: 0.5, -1: 0.5}
+    for J in range(1, Nc):
+        for I in range(1, Nc):
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    i, j = 2 * I + di, 2 * J + dj
+                    rows.append(fidx[j, i])
+                    cols.append(cidx[J, I])
+                    vals.append(w[di] * w[dj])
+    nf = (Nf - 1) ** 2
+    nc = (Nc - 1) ** 2
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
+def chebyshev_smooth(B, Dinv, t, x0, lo, hi, degree):
+    """Jacobi-preconditioned Chebyshev iteration on [lo, hi] (Saad, Iterative Methods, Alg. 12.1).
+
+    theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta.
+      r_0 = t - B x_0, rho_0 = 1/sigma, d_0 = D^{-1} r_0 / theta
+      x_{k+1} = x_k + d_k
+      r_{k+1} = t - B x_{k+1}, rho_{k+1} = 1/(2 sigma - rho_k)
+      d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^{-1} r_{k+1}
+    Returns x_degree (degree operator applications in total).
+    """
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma = theta / delta
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = t - B @ x
+    rho = 1.0 / sigma
+    d = Dinv * r / theta
+    for k in range(degree):
+        x = x + d
+        if k + 1 == degree:
+            break
+        r = t - B @ x
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (Dinv * r)
+        rho = rho_new
+    return x
+
+
+def power_mu(B, Dinv, level: int, iters: int) -> float:
+    """Estimate of the largest eigenvalue of D^{-1} B by `iters` power iterations.
+
+    x <- D^{-1} B x / |D^{-1} B x|_2 from the SplitMix64 start vector, then the
+    Rayleigh quotient x^T B x / x^T D x of the symmetric pencil (B, D).
+    """
+    x = start_vector(B.shape[0], level)
+    for _ in range(iters):
+        y = Dinv * (B @ x)
+        x = y / np.linalg.norm(y)
+    return float((x @ (B @ x)) / (x @ (x / Dinv)))
+
+
+class Hierarchy:
+    """Multigrid hierarchy for the blocks B(a) = M + dt*a*K on all levels.
+
+    Options mirror the GPU library's: coarse_n, cheb_degree, cheb_lo, cheb_hi,
+    power_its.
+    """
+
+    def __init__(self, N, kappa, dt, coarse_n=8, cheb_degree=2, cheb_lo=0.25, cheb_hi=1.1, power_its=15):
+        self.N = N
+        self.dt = dt
+        self.sizes = level_sizes(N, coarse_n)
+        self.deg = cheb_degree
+        self.lo = cheb_lo
+        self.hi = cheb_hi
+        self.power_its = power_its
+        self.M, self.K, self.P = [], [], []
+        kap = np.asarray(kappa, dtype=np.float64) if kappa is not None else np.ones(N * N)
+        for l, Nl in enumerate(self.sizes):
+            M, K = fem.assemble(Nl, kap)
+            self.M.append(M)
+            self.K.append(K)
+            if l + 1 < len(self.sizes):
+                self.P.append(prolongation(self.sizes[l + 1]))
+                kap = coarsen_kappa(Nl, kap)
+        self._blocks = {}
+
+    def block(self, a: float):
+        """Per-level operators for one diagonal block B(a): (B, Dinv, mu) lists and the coarse Cholesky factor."""
+        key = float(a)
+        if key not in self._blocks:
+            Bs, Dinvs, mus = [], [], []
+            for l in range(len(self.sizes)):
+                B = (self.M[l] + self.dt * a * self.K[l]).tocsr()
+                Dinv = 1.0 / B.diagonal()
+                Bs.append(B)
+                Dinvs.append(Dinv)
+                mus.append(power_mu(B, Dinv, l, self.power_its) if l + 1 < len(self.sizes) else None)
+            chol = sla.cho_factor(Bs[-1].toarray(), lower=True)
+            self._blocks[key] = (Bs, Dinvs, mus, chol)
+        return self._blocks[key]
+
+    def vcycle(self, a: float, t: np.ndarray, level: int = 0) -> np.ndarray:
+        """One V-cycle for B(a) x = t with zero initial guess on `level`."""
+        Bs, Dinvs, mus, chol = self.block(a)
+        if level == len(self.sizes) - 1:
+            return sla.cho_solve(chol, t)
+        B, Dinv, mu = Bs[level], Dinvs[level], mus[level]
+        lo, hi = self.lo * mu, self.hi * mu
+        x = chebyshev_smooth(B, Dinv, t, np.zeros_like(t), lo, hi, self.deg)
+        r = t - B @ x
+        P = self.P[level]
+        e = self.vcycle(a, P.T @ r, level + 1)
+        x = x + P @ e
+        x = chebyshev_smooth(B, Dinv, t, x, lo, hi, self.deg)
+        return x
+
+
+def apply_block_preconditioner(kind, A, dt, K, v, block_solve):
+    """Apply P^{-1} for the AI-form stage preconditioner.
+
+    kind: "jacobi" (P_D) or "gs_lower" (P_L). v is stage-major (s*n,).
+    block_solve(i, t) must return (an approximation of) B_i^{-1} t with
+    B_i = M + dt*a_ii*K.
+    """
+    A = np.asarray(A)
+    s = A.shape[0]
+    V = np.asarray(v).reshape(s, -1)
+    Z = np.zeros_like(V)
+    for i in range(s):
+        t = V[i].copy()
+        if kind == "gs_lower":
+            w = np.zeros_like(t)
+            for j in range(i):
+                w += A[i, j] * Z[j]
+            t = t - dt * (K @ w)
+        elif kind != "jacobi":
+            raise ValueError(kind)
+        Z[i] = block_solve(i, t)
+    return Z.ravel()
+
+
+def exact_block_solver(M, K, A, dt):
+    """block_solve that inverts every diagonal block B_i exactly (sparse LU)."""
+    A = np.asarray(A)
+    lus = [spla.splu((M + dt * A[i, i] * K).tocsc()) for i in range(A.shape[0])]
+    return lambda i, t: lus[i].solve(t)
+
+
+def vcycle_block_solver(hier: Hierarchy, A):
+    """block_solve that applies one V-cycle of `hier` to every diagonal block."""
+    A = np.asarray(A)
+    return lambda i, t: hier.vcycle(A[i, i], t)
