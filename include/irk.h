@@ -1,0 +1,187 @@
+/*
+ * irk.h -- C ABI of the MI355X stage solver for fully implicit Runge-Kutta
+ * time stepping of  M u' = -K u + F  (Q1 finite elements, uniform grid).
+ *
+ * Problem statement (Kirby & MacLachlan, "Extending Irksome", Section 2 and
+ * Section 3, eq:block_struct_AI): one time step of an s-stage Runge-Kutta method
+ * with Butcher tableau (A, b, c) solves the stage-coupled linear system
+ *
+ *     (I_s (x) M + dt * A (x) K) k = f,     f_i = -K u^n + F,
+ *
+ * for the stage derivatives k = (k_1, ..., k_s) and updates
+ * u^{n+1} = u^n + dt * sum_i b_i k_i.  M is the Q1 consistent mass matrix and K
+ * the stiffness matrix of div(kappa grad u) with per-element kappa on the
+ * uniform N x N grid of the unit square; homogeneous Dirichlet data are imposed
+ * as the paper's "DAE-type" boundary conditions (Section 2.1), which for g = 0
+ * and invertible A make every stage vanish on the boundary.
+ *
+ * The system is solved by right-preconditioned FGMRES. The preconditioner is the
+ * block Jacobi (eq:pcbjac) or block lower Gauss-Seidel (eq:pcbgs) stage
+ * preconditioner, in the AI form  I (x) M + dt * Atil (x) K  with Atil = D or
+ * L + D of A = L + D + U; each diagonal block M + dt*a_ii*K is approximated by one
+ * geometric multigrid V-cycle (Section 3.1).
+ *
+ * Conventions for every entry point:
+ *  - Return value: IRK_OK (0) or a negative irk_status. After an error,
+ *    irk_last_error() returns a message for the calling thread.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory. The caller owns every pointer passed in
+ *    and keeps it valid for the duration of the call. The library copies what
+ *    it keeps (kappa, the tableau, the options) and owns its workspace; the
+ *    destroy functions free it.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream). All device
+ *    work is enqueued on it. Entry points that make convergence decisions
+ *    (irk_solve_stages, irk_advance, irk_adjoint) synchronise the stream before
+ *    they return; the others only enqueue work.
+ *  - Nodal vectors use the compact interior layout: the n = (N-1)^2 interior
+ *    nodes, row-major by y with x fastest; node (i, j) at (i/N, j/N),
+ *    1 <= i, j <= N-1, sits at index (j-1)*(N-1) + (i-1). A stage block is s
+ *    such vectors one after the other (stage-major), s*n doubles.
+ *  - Element fields use the layout: element (ex, ey) covering
+ *    [ex/N,(ex+1)/N] x [ey/N,(ey+1)/N] sits at index ey*N + ex, N*N doubles.
+ */
+#ifndef IRK_H
+#define IRK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IRK_OK = 0,
+  IRK_EINVAL = -1,      /* invalid argument (message says which)               */
+  IRK_ENOMEM = -2,      /* device or host allocation failed                    */
+  IRK_EHIP = -3,        /* a HIP runtime call failed                           */
+  IRK_ENOCONV = -4,     /* FGMRES missed rtol within max_it                    */
+  IRK_EBREAKDOWN = -5   /* non-finite value met inside the Krylov iteration    */
+} irk_status;
+
+enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1 };            /* eq:pcbjac, eq:pcbgs */
+enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precision */
+enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1 };    /* Gram-Schmidt variant */
+enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial guess */
+
+/* Butcher tableau (Section 2): A is s x s row-major, b and c have s entries.
+ * Host memory; copied at stepper creation. */
+typedef struct {
+  int s;
+  const double *A;
+  const double *b;
+  const double *c;
+} irk_tableau;
+
+/* Solver options; fill with irk_options_default() and override fields. */
+typedef struct {
+  int precond;        /* IRK_PC_JACOBI or IRK_PC_GS_LOWER                         */
+  double rtol;        /* stop when |f - Acal k|_2 <= rtol * |f|_2 (true residual)  */
+  int restart;        /* FGMRES restart length m, 1..32                           */
+  int max_it;         /* total FGMRES iterations allowed per stage solve          */
+  int mg_coarse_n;    /* coarsening stops before a level below this many elements */
+  int cheb_degree;    /* Chebyshev smoothing degree, 1..3                          */
+  double cheb_lo;     /* smoothing interval [cheb_lo*mu, cheb_hi*mu]              */
+  double cheb_hi;
+  int power_its;      /* power iterations for the largest eigenvalue mu            */
+  int mg_precision;   /* IRK_F64, IRK_F32 or IRK_BF16 (storage; BF16 computes in FP32) */
+  int orth;           /* IRK_ORTH_CGS2 or IRK_ORTH_CGS_SELECTIVE                  */
+  int initial_guess;  /* IRK_GUESS_ZERO or IRK_GUESS_PREV (previous step's k)     */
+} irk_options;
+
+/* Per-call statistics (host struct, filled if non-NULL). */
+typedef struct {
+  int steps_done;        /* time steps completed successfully                */
+  int fgmres_its_total;  /* FGMRES iterations summed over the solves          */
+  int fgmres_its_max;    /* largest iteration count of one solve              */
+  int restarts_total;    /* FGMRES restarts summed over the solves            */
+  int solves;            /* stage-system solves performed                     */
+  int forward_advances;  /* adjoint only: forward steps recomputed by revolve  */
+  double last_rel_resid; /* |f - Acal k| / |f| of the last solve               */
+  int failed_step;       /* index of the step that failed, -1 if none          */
+} irk_stats;
+
+typedef struct irk_problem irk_problem;
+typedef struct irk_stepper irk_stepper;
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *irk_last_error(void);
+
+/* Defaults: GS_LOWER, rtol 1e-10, restart 30, max_it 300, coarse 8, Chebyshev
+ * degree 2 on [0.25 mu, 1.1 mu] (the interval of Section 4.3), 15 power
+ * iterations, FP64 multigrid, CGS2, zero initial guess. */
+void irk_options_default(irk_options *opts);
+
+/* Problem: the grid and the diffusivity. N >= 2 elements per side; kappa is a
+ * device array of N*N doubles (element layout), copied; every entry must be
+ * finite and > 0 (IRK_EINVAL otherwise). The multigrid needs N = Nc * 2^L with
+ * (Nc-1)^2 <= 1024; other N are accepted for the operators alone. */
+int irk_problem_create(irk_problem **out, int N, const double *kappa, void *stream);
+void irk_problem_destroy(irk_problem *p);
+
+/* y = M x on one nodal vector (device, n doubles each; x and y must not overlap). */
+int irk_apply_mass(const irk_problem *p, const double *x, double *y, void *stream);
+
+/* y = K x (device, n doubles each; no overlap). */
+int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *stream);
+
+/* Stepper: a tableau, a time step and solver options on a problem; sets up the
+ * multigrid hierarchy (level diffusivities, power-iteration estimates of mu per
+ * level and diagonal block, the coarsest-level inverse) and the Krylov
+ * workspace. Every eigenvalue of A must have positive real part and every
+ * a_ii > 0 (IRK_EINVAL otherwise). The problem must outlive the stepper. */
+int irk_stepper_create(irk_stepper **out, const irk_problem *p, const irk_tableau *tab,
+                       double dt, const irk_options *opts, void *stream);
+void irk_stepper_destroy(irk_stepper *st);
+
+/* a1 (Section 2, eq:rkheat): f_i = -K u + F for every stage i. u: device n; F: device
+ * n or NULL (F = 0); f: device s*n. */
+int irk_stage_rhs(const irk_stepper *st, const double *u, const double *F, double *f, void *stream);
+
+/* a2 (eq:block_struct_AI): y = (I (x) M + dt * A (x) K) x, or with A^T when transpose != 0.
+ * x, y: device s*n, no overlap. */
+int irk_apply_stage_operator(const irk_stepper *st, const double *x, double *y, int transpose, void *stream);
+
+/* a3 (eq:pcbjac / eq:pcbgs, AI form): z = P^{-1} v with the stepper's block preconditioner,
+ * every diagonal block solve replaced by one V-cycle. v, z: device s*n. */
+int irk_apply_preconditioner(const irk_stepper *st, const double *v, double *z, int transpose, void *stream);
+
+/* a4 (Section 3.1 diagonal blocks): z = one V-cycle for (M + dt*a_ii*K) z = t with zero
+ * initial guess, for stage `stage` (0-based). t, z: device n. */
+int irk_vcycle(const irk_stepper *st, int stage, const double *t, double *z, void *stream);
+
+/* a5: solve (I (x) M + dt*A (x) K) k = f (A^T when transpose != 0) by FGMRES to the
+ * stepper's rtol from a zero initial guess. f, k: device s*n. Synchronises. */
+int irk_solve_stages(irk_stepper *st, const double *f, double *k, int transpose, irk_stats *stats, void *stream);
+
+/* a1+a5+a6: advance u (device n, in/out) by nsteps time steps of size dt with forcing F
+ * (device n or NULL), u^{n+1} = u^n + dt * sum_i b_i k_i. On IRK_ENOCONV u holds the last
+ * step that converged and stats->failed_step names the failing step. Synchronises. */
+int irk_advance(irk_stepper *st, double *u, const double *F, int nsteps, irk_stats *stats, void *stream);
+
+/* a8+a9: discrete adjoint of nsteps steps from u0 (device n) with F = 0. Given
+ * lambda_T = dJ/du_N (device n) it returns lambda_0 = dJ/du_0 (device n, may be NULL) and
+ * grad_logkappa = dJ/dlog(kappa) (device N*N, element layout, may be NULL). The forward
+ * states are recomputed from nsnap >= 1 snapshots (one of them u0) by the optimal binomial
+ * checkpointing schedule. Synchronises. */
+int irk_adjoint(irk_stepper *st, const double *u0, int nsteps, int nsnap, const double *lambda_T,
+                double *lambda_0, double *grad_logkappa, irk_stats *stats, void *stream);
+
+/* a9 (host only): the binomial checkpointing schedule for nsteps steps and nsnap slots.
+ * Writes up to cap actions as pairs (kind, arg) into actions (host int[2*cap]);
+ * kind 0 = advance arg steps, 1 = store the current state in slot arg,
+ * 2 = restore slot arg, 3 = reverse the step starting at the current state
+ * (recompute its stages, solve its adjoint). *count receives the number of actions
+ * and *advances the number of forward steps outside reversals. Returns
+ * IRK_EINVAL if cap is too small (with *count set to the size needed). */
+int irk_revolve_schedule(int nsteps, int nsnap, int *actions, int cap, int *count, int *advances);
+
+/* Sizes: n = (N-1)^2 interior nodes and s stages of a stepper. */
+int irk_stepper_sizes(const irk_stepper *st, int *N, int *s, int *levels);
+
+/* The power-iteration estimate mu of the largest eigenvalue of D^{-1}(M + dt*a_ii*K) on
+ * multigrid level `level` (0 = finest) for stage `stage`; *mu = 0 on the coarsest level. */
+int irk_stepper_mu(const irk_stepper *st, int stage, int level, double *mu);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRK_H */

@@ -1,0 +1,137 @@
+// Internal declarations of the MI355X stage solver: data layout, kernel launch
+// wrappers and the runtime objects behind the C ABI of include/irk.h.
+//
+// Device data layout ("padded planes"). A level with N elements per side stores
+// a nodal field as (N+1) rows of `pitch` values (pitch = N+1 rounded up to a
+// multiple of 16, so every row starts on a 128-byte boundary for FP64). Node
+// (i, j) lives at j*pitch + i for 0 <= i, j <= N; the boundary ring and the row
+// padding hold zeros at all times, so every 9-point stencil at an interior node
+// reads valid memory without branches, and whole-vector Krylov operations can
+// run over the flat array. A stage block is s planes back to back. A per-element
+// field uses N rows of the same pitch: element (ex, ey) at ey*pitch + ex.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace irk {
+
+constexpr int kMaxStages = 8;
+constexpr int kMaxDeg = 3;
+constexpr int kMaxRestart = 64;
+constexpr int kMaxCoarse = 1024;  // unknowns of the dense coarsest-level solve
+
+struct bf16 {
+  uint16_t u;
+};
+
+struct Geom {
+  int N;       // elements per side
+  int pitch;   // values per row
+  long plane;  // (N+1)*pitch values per nodal plane
+  double h;    // 1/N
+};
+
+inline int pitch_for(int N) { return ((N + 1 + 15) / 16) * 16; }
+inline Geom make_geom(int N) {
+  Geom g;
+  g.N = N;
+  g.pitch = pitch_for(N);
+  g.plane = (long)(N + 1) * g.pitch;
+  g.h = 1.0 / N;
+  return g;
+}
+
+// s x s coefficient matrix passed by value to kernels
+struct Coefs {
+  double a[kMaxStages * kMaxStages];
+};
+
+// Chebyshev-Jacobi smoothing coefficients for one (level, diagonal block).
+// x_1 = x_0 + c0 D^{-1} r_0;  x_{k+1} = x_k + beta[k] (x_k - x_{k-1}) + gam[k] D^{-1} r_k.
+struct MGCoef {
+  double alpha;  // dt * a_ii
+  double m;      // h^2 / 36 (mass stencil scale)
+  double c0;
+  double beta[kMaxDeg];
+  double gam[kMaxDeg];
+  int deg;
+};
+
+// ---------------------------------------------------------------- layout (k_stencil.hip)
+void launch_pack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st);
+void launch_unpack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st);
+void launch_pack_elem(const double* src, double* dst, Geom g, hipStream_t st);
+void launch_unpack_elem(const double* src, double* dst, Geom g, hipStream_t st);
+void launch_check_kappa(const double* kappa, int count, int* bad, hipStream_t st);
+void launch_cast_f32(const double* src, float* dst, long count, hipStream_t st);
+void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, hipStream_t st);
+
+// ---------------------------------------------------------------- stencils (k_stencil.hip)
+// y = (I (x) M + dt*A (x) K) x  (coefficients `a`, row-major s x s); if f != nullptr: y = f - that.
+void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
+                           const Coefs& a, double dt, hipStream_t st);
+// f_i = -K u + F (F may be null), i = 0..s-1
+void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st);
+// y = M x or y = K x
+void launch_mass(const double* x, double* y, Geom g, hipStream_t st);
+void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st);
+// t = vscale * v - dt * K * sum_{j<i} coef[j] z_j  (z_j planes at z + j*plane)
+void launch_gs_couple(const double* v, double vscale, const double* z, int i, const Coefs& row, double dt,
+                      const double* kappa, double* t, Geom g, hipStream_t st);
+// u += dt * sum_i b_i k_i
+void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st);
+// f_i = dt * b_i * lam
+void launch_adjoint_rhs(const double* lam, double* f, int s, const Coefs& b, double dt, Geom g, hipStream_t st);
+// lam -= K * sum_i nu_i
+void launch_lambda_update(double* lam, const double* nu, int s, const double* kappa, Geom g, hipStream_t st);
+// g_e -= kappa_e * sum_i nu_i|_e^T Kref (u + dt sum_j a_ij k_j)|_e   (g padded element layout)
+void launch_kappa_grad(double* grad, const double* u, const double* k, const double* nu, const double* kappa, Geom g,
+                       int s, const Coefs& a, double dt, hipStream_t st);
+// power iteration helpers (FP64, setup): mode 0: y = B x, 1: y = D^{-1} B x, 2: y = D x
+void launch_level_apply(const double* x, double* y, const double* kappa, Geom g, double alpha, int mode,
+                        hipStream_t st);
+void launch_start_vector(double* x, Geom g, int level, hipStream_t st);
+void launch_scale(double* x, long n, const double* inv_norm2_src, hipStream_t st);
+
+// ---------------------------------------------------------------- multigrid (k_mg.hip)
+// prec: 0 = FP64 storage/compute, 1 = FP32, 2 = BF16 storage / FP32 compute.
+// DOWN: pre-smooth from zero on the fine level, write x, restrict the residual into tc (coarse).
+// t_is_f64: t is the FP64 Krylov vector (scaled by tscale) instead of level storage.
+void launch_mg_down(int prec, bool t_is_f64, const void* t, double tscale, void* x, void* tc, const void* kappa,
+                    Geom g, Geom gc, const MGCoef& c, hipStream_t st);
+// UP: x0 = x + P e, post-smooth, write out (FP64 if out_is_f64).
+void launch_mg_up(int prec, bool io_is_f64, const void* t, double tscale, const void* x, const void* e, void* out,
+                  const void* kappa, Geom g, Geom gc, const MGCoef& c, hipStream_t st);
+// coarsest level: out = Binv * t on the interior nodes
+void launch_mg_coarse(int prec, bool io_is_f64, const void* t, double tscale, void* out, const void* Binv, Geom g,
+                      hipStream_t st);
+
+// ---------------------------------------------------------------- Krylov (k_krylov.hip)
+struct OrthoArgs {
+  const double* V;       // basis vectors V_k = V + k*vstride
+  long vstride;
+  int nv;                // number of basis vectors (0..kMaxRestart)
+  double* w;             // vector updated in place when coef != nullptr
+  long len;              // values per vector
+  const double* coef;    // if set: w -= coef_sign * sum_k coef[k]*vscale[k]*V_k first
+  double coef_sign;
+  const double* vscale;  // per-vector scale (nullptr = 1)
+  int want_dots;         // compute dots[k] = vscale[k] * V_k . w (after the update)
+  const int* skip;       // if set and *skip == 0 the pass does nothing
+  double* result;        // [nv+1]: dots then |w|^2
+  double* sigma_out;     // if set: *sigma_out = 1/sqrt(|w|^2)
+  int* flag_out;         // if set: *flag_out = (|w|^2 < eta2 * *ref)
+  const double* ref;
+  double eta2;
+};
+struct ReduceWork {
+  double* partial;     // [max_blocks * (kMaxRestart+1)]
+  unsigned* counter;   // one zeroed counter
+  int max_blocks;
+};
+void launch_ortho(const OrthoArgs& a, const ReduceWork& w, hipStream_t st);
+
+}  // namespace irk

@@ -1,0 +1,367 @@
+// Geometric multigrid V-cycle kernels for one diagonal stage block
+// B = M + dt*a_ii*K (Section 3.1: the diagonal blocks of the block Jacobi /
+// Gauss-Seidel stage preconditioners are approximated by multigrid).
+//
+// One level of the V-cycle is two LDS-tiled kernels:
+//   DOWN: Jacobi-Chebyshev pre-smoothing from a zero guess, fused with the
+//         residual t - B x and its restriction P^T (full weighting) to the
+//         next coarser level; writes x (needed again on the way up) and the
+//         coarse right-hand side. Reads t and kappa once.
+//   UP:   bilinear prolongation and correction x + P e, fused with
+//         Jacobi-Chebyshev post-smoothing; writes the level's result.
+// Each block stages a tile of TX x TY nodes plus a halo (one node per fused
+// stencil application) of the fields in LDS; the valid region shrinks by one
+// node per stencil application until it is the tile. The diagonal D of B is
+// recomputed from the four element diffusivities wherever it is needed.
+// The coarsest level is solved with a precomputed dense inverse.
+//
+// Storage type TS (FP64, FP32 or BF16) holds the level vectors; arithmetic and
+// kappa use TC (FP64, or FP32 for both reduced-precision forms). TV is the type
+// of the finest level's right-hand side and result (the FP64 Krylov vectors).
+#include "irk_internal.h"
+
+namespace irk {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ float bf2f(uint16_t u) { return __uint_as_float(((uint32_t)u) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even (inputs are finite)
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+template <typename TC>
+__device__ __forceinline__ TC ld(const double* p) { return (TC)*p; }
+template <typename TC>
+__device__ __forceinline__ TC ld(const float* p) { return (TC)*p; }
+template <typename TC>
+__device__ __forceinline__ TC ld(const bf16* p) { return (TC)bf2f(p->u); }
+
+__device__ __forceinline__ void st(double* p, double v) { *p = v; }
+__device__ __forceinline__ void st(double* p, float v) { *p = (double)v; }
+__device__ __forceinline__ void st(float* p, float v) { *p = v; }
+__device__ __forceinline__ void st(float* p, double v) { *p = (float)v; }
+__device__ __forceinline__ void st(bf16* p, float v) { p->u = f2bf(v); }
+__device__ __forceinline__ void st(bf16* p, double v) { p->u = f2bf((float)v); }
+
+// B x and D at LDS node (li, lj); X has row length RX, K (element field) row length KX = RX + 1
+template <typename TC, int RX, int KX>
+__device__ __forceinline__ void bx_d(const TC* X, const TC* K, int li, int lj, TC m, TC alpha, TC& Bx, TC& D) {
+  const int p = lj * RX + li;
+  const int q = lj * KX + li;
+  const TC kSW = K[q], kSE = K[q + 1], kNW = K[q + KX], kNE = K[q + KX + 1];
+  const TC xc = X[p], xE = X[p + 1], xW = X[p - 1], xN = X[p + RX], xS = X[p - RX];
+  const TC xNE = X[p + RX + 1], xNW = X[p + RX - 1], xSE = X[p - RX + 1], xSW = X[p - RX - 1];
+  const TC ks = kSW + kSE + kNW + kNE;
+  const TC Kx = (TC)(2.0 / 3.0) * ks * xc -
+                (TC)(1.0 / 6.0) * ((kNE + kSE) * xE + (kNW + kSW) * xW + (kNE + kNW) * xN + (kSE + kSW) * xS) -
+                (TC)(1.0 / 3.0) * (kNE * xNE + kNW * xNW + kSE * xSE + kSW * xSW);
+  const TC Mx = m * ((TC)16 * xc + (TC)4 * (xE + xW + xN + xS) + (xNE + xNW + xSE + xSW));
+  Bx = Mx + alpha * Kx;
+  D = (TC)16 * m + alpha * (TC)(2.0 / 3.0) * ks;
+}
+
+template <typename TC, int KX>
+__device__ __forceinline__ TC diag_at(const TC* K, int li, int lj, TC m, TC alpha) {
+  const int q = lj * KX + li;
+  return (TC)16 * m + alpha * (TC)(2.0 / 3.0) * (K[q] + K[q + 1] + K[q + KX] + K[q + KX + 1]);
+}
+
+__device__ __forceinline__ bool interior(int i, int j, int N) { return i >= 1 && i <= N - 1 && j >= 1 && j <= N - 1; }
+
+template <typename TC, typename TK, int KX, int KY>
+__device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ kap, int ox, int oy, const Geom& g) {
+  for (int idx = threadIdx.x; idx < KX * KY; idx += NT) {
+    const int b = idx / KX, a = idx - b * KX;
+    const int ex = ox - 1 + a, ey = oy - 1 + b;
+    TC v = (TC)0;
+    if (ex >= 0 && ex < g.N && ey >= 0 && ey < g.N) v = (TC)kap[(long)ey * g.pitch + ex];
+    sK[idx] = v;
+  }
+}
+
+template <typename TV, typename TS, typename TC, int DEG, int TX, int TY>
+__global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, double tscale, TS* __restrict__ xout,
+                                                     TS* __restrict__ tc, const TC* __restrict__ kap, Geom g, Geom gc,
+                                                     MGCoef cf) {
+  constexpr int H = DEG + 1;
+  constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
+  constexpr int KX = RX + 1, KY = RY + 1;
+  __shared__ TC sK[KX * KY];
+  __shared__ TC sT[RX * RY];
+  __shared__ TC sA[RX * RY];
+  __shared__ TC sB[RX * RY];
+  const int N = g.N;
+  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  const int ox = i0 - H, oy = j0 - H;
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)tscale;
+
+  load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+  for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
+    const int lj = idx / RX, li = idx - lj * RX;
+    const int i = ox + li, j = oy + lj;
+    TC v = (TC)0;
+    if (interior(i, j, N)) v = ld<TC>(t + (long)j * g.pitch + i) * ts;
+    sT[idx] = v;
+    sA[idx] = (TC)0;
+  }
+  __syncthreads();
+  // first Chebyshev step from x0 = 0 is pointwise: x1 = c0 D^{-1} t
+  {
+    const TC c0 = (TC)cf.c0;
+    for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
+      const int lj = idx / RX, li = idx - lj * RX;
+      TC v = (TC)0;
+      if (interior(ox + li, oy + lj, N)) v = c0 * sT[idx] / diag_at<TC, KX>(sK, li, lj, m, alpha);
+      sB[idx] = v;
+    }
+  }
+  __syncthreads();
+  TC* cur = sB;
+  TC* prv = sA;
+#pragma unroll
+  for (int k = 1; k < DEG; ++k) {
+    const TC beta = (TC)cf.beta[k], gam = (TC)cf.gam[k];
+    const int w = RX - 2 * k, hgt = RY - 2 * k;
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = k + idx / w, li = k + idx % w;
+      if (!interior(ox + li, oy + lj, N)) continue;
+      TC Bx, D;
+      bx_d<TC, RX, KX>(cur, sK, li, lj, m, alpha, Bx, D);
+      const int p = lj * RX + li;
+      prv[p] = cur[p] + beta * (cur[p] - prv[p]) + gam * (sT[p] - Bx) / D;
+    }
+    __syncthreads();
+    TC* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  // smoothed x on the tile
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int lj = H + idx / TX, li = H + idx % TX;
+    const int i = ox + li, j = oy + lj;
+    if (interior(i, j, N)) st(xout + (long)j * g.pitch + i, cur[lj * RX + li]);
+  }
+  // residual on the tile plus one node
+  {
+    const int w = TX + 2, hgt = TY + 2;
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = H - 1 + idx / w, li = H - 1 + idx % w;
+      const int p = lj * RX + li;
+      TC r = (TC)0;
+      if (interior(ox + li, oy + lj, N)) {
+        TC Bx, D;
+        bx_d<TC, RX, KX>(cur, sK, li, lj, m, alpha, Bx, D);
+        r = sT[p] - Bx;
+      }
+      prv[p] = r;
+    }
+  }
+  __syncthreads();
+  // full-weighting restriction (P^T of bilinear interpolation) to coarse nodes centred in the tile
+  {
+    constexpr int CX = TX / 2, CY = TY / 2;
+    const int I0 = (i0 + 1) / 2, J0 = (j0 + 1) / 2;
+    for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
+      const int I = I0 + idx % CX, J = J0 + idx / CX;
+      if (I > gc.N - 1 || J > gc.N - 1) continue;
+      const int li = 2 * I - ox, lj = 2 * J - oy;
+      const TC* R = prv + lj * RX + li;
+      const TC v = R[0] + (TC)0.5 * (R[1] + R[-1] + R[RX] + R[-RX]) +
+                   (TC)0.25 * (R[RX + 1] + R[RX - 1] + R[-RX + 1] + R[-RX - 1]);
+      st(tc + (long)J * gc.pitch + I, v);
+    }
+  }
+}
+
+template <typename TS, typename TC>
+__device__ __forceinline__ TC prolong_at(const TS* __restrict__ e, int pc, int i, int j) {
+  const int I = i >> 1, J = j >> 1;
+  const TS* b = e + (long)J * pc + I;
+  const TC e00 = ld<TC>(b);
+  if (!(i & 1) && !(j & 1)) return e00;
+  if ((i & 1) && !(j & 1)) return (TC)0.5 * (e00 + ld<TC>(b + 1));
+  if (!(i & 1) && (j & 1)) return (TC)0.5 * (e00 + ld<TC>(b + pc));
+  return (TC)0.25 * (e00 + ld<TC>(b + 1) + ld<TC>(b + pc) + ld<TC>(b + pc + 1));
+}
+
+template <typename TV, typename TS, typename TC, int DEG, int TX, int TY>
+__global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, double tscale, const TS* __restrict__ x,
+                                                   const TS* __restrict__ e, TV* __restrict__ out,
+                                                   const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf) {
+  constexpr int H = DEG;
+  constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
+  constexpr int KX = RX + 1, KY = RY + 1;
+  __shared__ TC sK[KX * KY];
+  __shared__ TC sT[RX * RY];
+  __shared__ TC sA[RX * RY];
+  __shared__ TC sB[RX * RY];
+  const int N = g.N;
+  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  const int ox = i0 - H, oy = j0 - H;
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)tscale;
+
+  load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+  for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
+    const int lj = idx / RX, li = idx - lj * RX;
+    const int i = ox + li, j = oy + lj;
+    TC tv = (TC)0, xv = (TC)0;
+    if (interior(i, j, N)) {
+      const long p = (long)j * g.pitch + i;
+      tv = ld<TC>(t + p) * ts;
+      xv = ld<TC>(x + p) + prolong_at<TS, TC>(e, gc.pitch, i, j);
+    }
+    sT[idx] = tv;
+    sA[idx] = xv;
+    sB[idx] = (TC)0;
+  }
+  __syncthreads();
+  // first step from the corrected x0: x1 = x0 + c0 D^{-1} (t - B x0)
+  {
+    const TC c0 = (TC)cf.c0;
+    const int w = RX - 2, hgt = RY - 2;
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = 1 + idx / w, li = 1 + idx % w;
+      if (!interior(ox + li, oy + lj, N)) continue;
+      TC Bx, D;
+      bx_d<TC, RX, KX>(sA, sK, li, lj, m, alpha, Bx, D);
+      const int p = lj * RX + li;
+      sB[p] = sA[p] + c0 * (sT[p] - Bx) / D;
+    }
+  }
+  __syncthreads();
+  TC* cur = sB;
+  TC* prv = sA;
+#pragma unroll
+  for (int k = 1; k < DEG; ++k) {
+    const TC beta = (TC)cf.beta[k], gam = (TC)cf.gam[k];
+    const int w = RX - 2 * (k + 1), hgt = RY - 2 * (k + 1);
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = k + 1 + idx / w, li = k + 1 + idx % w;
+      if (!interior(ox + li, oy + lj, N)) continue;
+      TC Bx, D;
+      bx_d<TC, RX, KX>(cur, sK, li, lj, m, alpha, Bx, D);
+      const int p = lj * RX + li;
+      prv[p] = cur[p] + beta * (cur[p] - prv[p]) + gam * (sT[p] - Bx) / D;
+    }
+    __syncthreads();
+    TC* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int lj = H + idx / TX, li = H + idx % TX;
+    const int i = ox + li, j = oy + lj;
+    if (interior(i, j, N)) st(out + (long)j * g.pitch + i, cur[lj * RX + li]);
+  }
+}
+
+template <typename TI, typename TO, typename TC>
+__global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t, double tscale, TO* __restrict__ out,
+                                                       const TC* __restrict__ Binv, Geom g) {
+  __shared__ TC sv[kMaxCoarse];
+  const int m = g.N - 1;
+  const int n = m * m;
+  for (int q = threadIdx.x; q < n; q += NT) {
+    const int j = q / m + 1, i = q % m + 1;
+    sv[q] = ld<TC>(t + (long)j * g.pitch + i) * (TC)tscale;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += NT) {
+    const TC* row = Binv + (long)q * n;
+    TC acc = (TC)0;
+    for (int r = 0; r < n; ++r) acc += row[r] * sv[r];
+    const int j = q / m + 1, i = q % m + 1;
+    st(out + (long)j * g.pitch + i, acc);
+  }
+}
+
+constexpr int TXD = 64, TYD = 16;
+
+template <typename TV, typename TS, typename TC>
+void down_t(const void* t, double tscale, void* x, void* tc, const void* kap, Geom g, Geom gc, const MGCoef& c,
+            hipStream_t st) {
+  const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
+  const TV* tt = (const TV*)t;
+  TS* xx = (TS*)x;
+  TS* cc = (TS*)tc;
+  const TC* kk = (const TC*)kap;
+  switch (c.deg) {
+    case 1: mg_down_kernel<TV, TS, TC, 1, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c); break;
+    case 2: mg_down_kernel<TV, TS, TC, 2, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c); break;
+    default: mg_down_kernel<TV, TS, TC, 3, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c); break;
+  }
+}
+
+template <typename TV, typename TS, typename TC>
+void up_t(const void* t, double tscale, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
+          const MGCoef& c, hipStream_t st) {
+  const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
+  const TV* tt = (const TV*)t;
+  const TS* xx = (const TS*)x;
+  const TS* ee = (const TS*)e;
+  TV* oo = (TV*)out;
+  const TC* kk = (const TC*)kap;
+  switch (c.deg) {
+    case 1: mg_up_kernel<TV, TS, TC, 1, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c); break;
+    case 2: mg_up_kernel<TV, TS, TC, 2, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c); break;
+    default: mg_up_kernel<TV, TS, TC, 3, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c); break;
+  }
+}
+
+}  // namespace
+
+void launch_mg_down(int prec, bool t_is_f64, const void* t, double tscale, void* x, void* tc, const void* kappa,
+                    Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
+  if (prec == 0) {
+    down_t<double, double, double>(t, tscale, x, tc, kappa, g, gc, c, st);
+  } else if (prec == 1) {
+    if (t_is_f64)
+      down_t<double, float, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+    else
+      down_t<float, float, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+  } else {
+    if (t_is_f64)
+      down_t<double, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+    else
+      down_t<bf16, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+  }
+}
+
+void launch_mg_up(int prec, bool io_is_f64, const void* t, double tscale, const void* x, const void* e, void* out,
+                  const void* kappa, Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
+  if (prec == 0) {
+    up_t<double, double, double>(t, tscale, x, e, out, kappa, g, gc, c, st);
+  } else if (prec == 1) {
+    if (io_is_f64)
+      up_t<double, float, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+    else
+      up_t<float, float, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+  } else {
+    if (io_is_f64)
+      up_t<double, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+    else
+      up_t<bf16, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+  }
+}
+
+void launch_mg_coarse(int prec, bool io_is_f64, const void* t, double tscale, void* out, const void* Binv, Geom g,
+                      hipStream_t st) {
+  if (prec == 0) {
+    mg_coarse_kernel<double, double, double><<<1, NT, 0, st>>>((const double*)t, tscale, (double*)out,
+                                                              (const double*)Binv, g);
+  } else if (io_is_f64) {
+    mg_coarse_kernel<double, double, float><<<1, NT, 0, st>>>((const double*)t, tscale, (double*)out,
+                                                             (const float*)Binv, g);
+  } else if (prec == 1) {
+    mg_coarse_kernel<float, float, float><<<1, NT, 0, st>>>((const float*)t, tscale, (float*)out,
+                                                           (const float*)Binv, g);
+  } else {
+    mg_coarse_kernel<bf16, bf16, float><<<1, NT, 0, st>>>((const bf16*)t, tscale, (bf16*)out, (const float*)Binv, g);
+  }
+}
+
+}  // namespace irk

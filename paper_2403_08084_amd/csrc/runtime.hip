@@ -1,0 +1,1142 @@
+// Host runtime behind the C ABI: problem and stepper objects, multigrid setup,
+// the FGMRES driver, the time loop and the adjoint with binomial checkpointing.
+// Every floating-point step of the solve runs in the kernels of k_*.hip; the
+// host only orchestrates launches, runs the (m+1) x m Hessenberg least-squares
+// update, and makes the convergence decisions.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/irk.h"
+#include "irk_internal.h"
+
+using namespace irk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(IRK_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(expr)              \
+  do {                         \
+    int r_ = (expr);           \
+    if (r_ != IRK_OK) return r_; \
+  } while (0)
+
+int dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(IRK_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  return IRK_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(IRK_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return IRK_OK;
+}
+
+size_t storage_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+
+}  // namespace
+
+struct irk_problem {
+  int N = 0;
+  Geom g{};
+  double* kappa = nullptr;  // padded element layout, FP64
+};
+
+namespace {
+
+struct Level {
+  Geom g{};
+  double* kap64 = nullptr;  // FP64 diffusivity (level 0: the problem's)
+  void* kapc = nullptr;     // diffusivity in the multigrid compute type
+  void* t = nullptr;        // right-hand side (levels >= 1)
+  void* x = nullptr;        // pre-smoothed iterate (levels < L-1)
+  void* e = nullptr;        // level result / coarse correction (levels >= 1)
+  bool own64 = false;
+};
+
+}  // namespace
+
+struct irk_stepper {
+  const irk_problem* prob = nullptr;
+  int s = 0;
+  double A[kMaxStages * kMaxStages] = {};
+  double b[kMaxStages] = {};
+  double c[kMaxStages] = {};
+  double dt = 0;
+  irk_options opt{};
+  int prec = 0;
+  Geom g{};
+  long vlen = 0;  // s * plane
+  std::vector<Level> lv;
+  std::vector<MGCoef> coef;   // [stage * L + level]
+  std::vector<double> mu;     // [stage * L + level]
+  std::vector<void*> binv;    // per stage, coarsest-level inverse in the compute type
+  // Krylov workspace
+  double* V = nullptr;    // (m+1) vectors
+  double* Z = nullptr;    // m vectors
+  double* f = nullptr;    // right-hand side (s planes)
+  double* k = nullptr;    // solution (s planes)
+  double* kprev = nullptr;
+  double* tmp = nullptr;  // s planes
+  double* tmp2 = nullptr; // s planes
+  double* u = nullptr;    // state plane
+  double* Fp = nullptr;   // forcing plane
+  double* dres = nullptr; // device results: [4][kMaxRestart+1] + sigma[kMaxRestart+1] + y[kMaxRestart]
+  int* dflag = nullptr;
+  double* hres = nullptr; // pinned host mirror of dres
+  ReduceWork rw{};
+  bool have_prev = false;
+};
+
+namespace {
+
+constexpr int RSTRIDE = kMaxRestart + 2;
+double* res_slot(irk_stepper* st, int which) { return st->dres + (long)which * RSTRIDE; }
+double* sigma_dev(irk_stepper* st) { return st->dres + 4L * RSTRIDE; }
+double* ycoef_dev(irk_stepper* st) { return st->dres + 5L * RSTRIDE; }
+constexpr long DRES_LEN = 6L * RSTRIDE;
+
+Coefs coefs_of(const irk_stepper* st, bool trans) {
+  Coefs a{};
+  for (int i = 0; i < st->s; ++i)
+    for (int j = 0; j < st->s; ++j) a.a[i * kMaxStages + j] = trans ? st->A[j * st->s + i] : st->A[i * st->s + j];
+  return a;
+}
+
+Coefs b_of(const irk_stepper* st) {
+  Coefs b{};
+  for (int i = 0; i < st->s; ++i) b.a[i] = st->b[i];
+  return b;
+}
+
+// ------------------------------------------------------------------ reductions
+
+int ortho(irk_stepper* st, const OrthoArgs& a, hipStream_t s) {
+  launch_ortho(a, st->rw, s);
+  return check_launch();
+}
+
+OrthoArgs ortho_base() {
+  OrthoArgs a{};
+  a.coef_sign = 1.0;
+  a.eta2 = 0.5;
+  return a;
+}
+
+// |x|^2 into res (device), optionally 1/|x| into sig
+int norm2(irk_stepper* st, const double* x, long len, double* res, double* sig, hipStream_t s) {
+  OrthoArgs a = ortho_base();
+  a.nv = 0;
+  a.w = const_cast<double*>(x);
+  a.len = len;
+  a.result = res;
+  a.sigma_out = sig;
+  return ortho(st, a, s);
+}
+
+// res[0] = x . y
+int dot(irk_stepper* st, const double* x, const double* y, long len, double* res, hipStream_t s) {
+  OrthoArgs a = ortho_base();
+  a.V = x;
+  a.vstride = 0;
+  a.nv = 1;
+  a.w = const_cast<double*>(y);
+  a.len = len;
+  a.want_dots = 1;
+  a.result = res;
+  return ortho(st, a, s);
+}
+
+// ------------------------------------------------------------------ multigrid setup
+
+void cheb_coef(double mu, const irk_options& o, MGCoef& c) {
+  const double lo = o.cheb_lo * mu, hi = o.cheb_hi * mu;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  c.deg = o.cheb_degree;
+  c.c0 = 1.0 / theta;
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < kMaxDeg; ++k) {
+    c.beta[k] = 0.0;
+    c.gam[k] = 0.0;
+  }
+  for (int k = 1; k < o.cheb_degree; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c.beta[k] = rn * rho;
+    c.gam[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+// Largest eigenvalue of D^{-1}B on one level by power iteration from the SplitMix64 start vector.
+int power_mu(irk_stepper* st, int level, double alpha, double* mu_out, hipStream_t s) {
+  const Level& L = st->lv[level];
+  const Geom& g = L.g;
+  double* x = st->tmp;
+  double* y = st->tmp + g.plane;
+  double* z = st->tmp2;
+  HIPCHK(hipMemsetAsync(x, 0, g.plane * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(y, 0, g.plane * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(z, 0, g.plane * sizeof(double), s));
+  launch_start_vector(x, g, level, s);
+  double* r = res_slot(st, 0);
+  for (int it = 0; it < st->opt.power_its; ++it) {
+    launch_level_apply(x, y, L.kap64, g, alpha, 1, s);
+    CHK(norm2(st, y, g.plane, r, nullptr, s));
+    launch_scale(y, g.plane, r, s);
+    std::swap(x, y);
+  }
+  launch_level_apply(x, y, L.kap64, g, alpha, 0, s);  // B x
+  launch_level_apply(x, z, L.kap64, g, alpha, 2, s);  // D x
+  CHK(dot(st, x, y, g.plane, res_slot(st, 1), s));
+  CHK(dot(st, x, z, g.plane, res_slot(st, 2), s));
+  CHK(check_launch());
+  double h[2];
+  HIPCHK(hipMemcpyAsync(&h[0], res_slot(st, 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&h[1], res_slot(st, 2), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *mu_out = h[0] / h[1];
+  if (!(std::isfinite(*mu_out) && *mu_out > 0)) return fail(IRK_EINVAL, "power iteration produced a non-positive mu");
+  return IRK_OK;
+}
+
+// Dense inverse of the coarsest-level block M + alpha*K (interior nodes), by Cholesky.
+int coarse_inverse(const std::vector<double>& kap, int N, double alpha, std::vector<double>& inv) {
+  const int m = N - 1, n = m * m;
+  const double h = 1.0 / N;
+  const double Kr[4][4] = {{4, -1, -2, -1}, {-1, 4, -1, -2}, {-2, -1, 4, -1}, {-1, -2, -1, 4}};
+  const double Mr[4][4] = {{4, 2, 1, 2}, {2, 4, 2, 1}, {1, 2, 4, 2}, {2, 1, 2, 4}};
+  const int dx[4] = {0, 1, 1, 0}, dy[4] = {0, 0, 1, 1};
+  std::vector<double> B((size_t)n * n, 0.0);
+  for (int ey = 0; ey < N; ++ey)
+    for (int ex = 0; ex < N; ++ex) {
+      int idx[4];
+      for (int a = 0; a < 4; ++a) {
+        const int i = ex + dx[a], j = ey + dy[a];
+        idx[a] = (i >= 1 && i <= m && j >= 1 && j <= m) ? (j - 1) * m + (i - 1) : -1;
+      }
+      const double ke = kap[(size_t)ey * N + ex];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c)
+          if (idx[a] >= 0 && idx[c] >= 0)
+            B[(size_t)idx[a] * n + idx[c]] += alpha * ke * Kr[a][c] / 6.0 + h * h * Mr[a][c] / 36.0;
+    }
+  // Cholesky B = L L^T (lower, in place)
+  for (int j = 0; j < n; ++j) {
+    double d = B[(size_t)j * n + j];
+    for (int k2 = 0; k2 < j; ++k2) d -= B[(size_t)j * n + k2] * B[(size_t)j * n + k2];
+    if (!(d > 0)) return fail(IRK_EINVAL, "coarsest-level block is not positive definite");
+    d = std::sqrt(d);
+    B[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = B[(size_t)i * n + j];
+      for (int k2 = 0; k2 < j; ++k2) v -= B[(size_t)i * n + k2] * B[(size_t)j * n + k2];
+      B[(size_t)i * n + j] = v / d;
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    std::fill(col.begin(), col.end(), 0.0);
+    col[c] = 1.0;
+    for (int i = 0; i < n; ++i) {  // L y = e_c
+      double v = col[i];
+      for (int k2 = 0; k2 < i; ++k2) v -= B[(size_t)i * n + k2] * col[k2];
+      col[i] = v / B[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+      double v = col[i];
+      for (int k2 = i + 1; k2 < n; ++k2) v -= B[(size_t)k2 * n + i] * col[k2];
+      col[i] = v / B[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = col[i];
+  }
+  return IRK_OK;
+}
+
+int setup_multigrid(irk_stepper* st, hipStream_t s) {
+  const irk_problem* p = st->prob;
+  std::vector<int> sizes{p->N};
+  while (sizes.back() % 2 == 0 && sizes.back() / 2 >= st->opt.mg_coarse_n) sizes.push_back(sizes.back() / 2);
+  const int Nc = sizes.back();
+  if ((long)(Nc - 1) * (Nc - 1) > kMaxCoarse)
+    return fail(IRK_EINVAL, "multigrid needs N = Nc * 2^L with (Nc-1)^2 <= 1024; N = " + std::to_string(p->N) +
+                                " stops at a " + std::to_string(Nc) + "^2 coarsest grid");
+  const int L = (int)sizes.size();
+  const size_t tsz = storage_bytes(st->prec);
+  st->lv.resize(L);
+  for (int l = 0; l < L; ++l) {
+    Level& lev = st->lv[l];
+    lev.g = make_geom(sizes[l]);
+    const long kcount = (long)lev.g.N * lev.g.pitch;
+    if (l == 0) {
+      lev.kap64 = p->kappa;
+    } else {
+      CHK(dev_alloc((void**)&lev.kap64, kcount * sizeof(double)));
+      lev.own64 = true;
+      launch_coarsen_kappa(st->lv[l - 1].kap64, lev.kap64, st->lv[l - 1].g, lev.g, s);
+    }
+    if (st->prec == 0) {
+      lev.kapc = lev.kap64;
+    } else {
+      CHK(dev_alloc(&lev.kapc, kcount * sizeof(float)));
+      launch_cast_f32(lev.kap64, (float*)lev.kapc, kcount, s);
+    }
+    const size_t pb = lev.g.plane * tsz;
+    if (l >= 1) {
+      CHK(dev_alloc(&lev.t, pb));
+      CHK(dev_alloc(&lev.e, pb));
+      HIPCHK(hipMemsetAsync(lev.t, 0, pb, s));
+      HIPCHK(hipMemsetAsync(lev.e, 0, pb, s));
+    }
+    if (l < L - 1) {
+      CHK(dev_alloc(&lev.x, pb));
+      HIPCHK(hipMemsetAsync(lev.x, 0, pb, s));
+    }
+  }
+  CHK(check_launch());
+  // Chebyshev coefficients per (stage, level) from power-iteration estimates
+  st->coef.assign((size_t)st->s * L, MGCoef{});
+  st->mu.assign((size_t)st->s * L, 0.0);
+  for (int i = 0; i < st->s; ++i) {
+    const double alpha = st->dt * st->A[i * st->s + i];
+    for (int l = 0; l < L; ++l) {
+      MGCoef& c = st->coef[(size_t)i * L + l];
+      c.alpha = alpha;
+      c.m = st->lv[l].g.h * st->lv[l].g.h / 36.0;
+      c.deg = st->opt.cheb_degree;
+      if (l < L - 1) {
+        // reuse the estimate of an earlier stage with the same diagonal entry
+        double mu = 0;
+        for (int i2 = 0; i2 < i; ++i2)
+          if (st->A[i2 * st->s + i2] == st->A[i * st->s + i]) mu = st->mu[(size_t)i2 * L + l];
+        if (mu == 0) CHK(power_mu(st, l, alpha, &mu, s));
+        st->mu[(size_t)i * L + l] = mu;
+        cheb_coef(mu, st->opt, c);
+      }
+    }
+  }
+  // coarsest-level inverses
+  const Level& lc = st->lv[L - 1];
+  std::vector<double> kpad((size_t)lc.g.N * lc.g.pitch), kc((size_t)lc.g.N * lc.g.N);
+  HIPCHK(hipMemcpyAsync(kpad.data(), lc.kap64, kpad.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int ey = 0; ey < lc.g.N; ++ey)
+    for (int ex = 0; ex < lc.g.N; ++ex) kc[(size_t)ey * lc.g.N + ex] = kpad[(size_t)ey * lc.g.pitch + ex];
+  st->binv.assign(st->s, nullptr);
+  const int nc = (lc.g.N - 1) * (lc.g.N - 1);
+  for (int i = 0; i < st->s; ++i) {
+    std::vector<double> inv;
+    CHK(coarse_inverse(kc, lc.g.N, st->dt * st->A[i * st->s + i], inv));
+    if (st->prec == 0) {
+      CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(double)));
+      HIPCHK(hipMemcpy(st->binv[i], inv.data(), (size_t)nc * nc * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(inv.begin(), inv.end());
+      CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(float)));
+      HIPCHK(hipMemcpy(st->binv[i], f.data(), (size_t)nc * nc * sizeof(float), hipMemcpyHostToDevice));
+    }
+  }
+  return IRK_OK;
+}
+
+// ------------------------------------------------------------------ preconditioner
+
+// out = one V-cycle for block `stage` applied to tscale * t (FP64 padded planes)
+int vcycle(irk_stepper* st, int stage, const double* t, double tscale, double* out, hipStream_t s) {
+  const int L = (int)st->lv.size();
+  const MGCoef* cf = &st->coef[(size_t)stage * L];
+  const int pr = st->prec;
+  if (L == 1) {
+    launch_mg_coarse(pr, true, t, tscale, out, st->binv[stage], st->lv[0].g, s);
+    return check_launch();
+  }
+  std::vector<Level>& lv = st->lv;
+  launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
+  for (int l = 1; l < L - 1; ++l)
+    launch_mg_down(pr, false, lv[l].t, 1.0, lv[l].x, lv[l + 1].t, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+  launch_mg_coarse(pr, false, lv[L - 1].t, 1.0, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
+  for (int l = L - 2; l >= 1; --l)
+    launch_mg_up(pr, false, lv[l].t, 1.0, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+  launch_mg_up(pr, true, t, tscale, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
+  return check_launch();
+}
+
+// z = P^{-1} (vscale * v), block Jacobi or block lower Gauss-Seidel in the AI form
+int precondition(irk_stepper* st, const double* v, double vscale, double* z, bool trans, hipStream_t s) {
+  const long plane = st->g.plane;
+  const Coefs a = coefs_of(st, trans);
+  for (int i = 0; i < st->s; ++i) {
+    const double* vi = v + i * plane;
+    double* zi = z + i * plane;
+    if (st->opt.precond == IRK_PC_GS_LOWER && i > 0) {
+      Coefs row{};
+      for (int j = 0; j < i; ++j) row.a[j] = a.a[i * kMaxStages + j];
+      double* t = st->tmp2;
+      launch_gs_couple(vi, vscale, z, i, row, st->dt, st->prob->kappa, t, st->g, s);
+      CHK(vcycle(st, i, t, 1.0, zi, s));
+    } else {
+      CHK(vcycle(st, i, vi, vscale, zi, s));
+    }
+  }
+  return check_launch();
+}
+
+int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s) {
+  launch_stage_operator(x, y, f, st->prob->kappa, st->g, st->s, coefs_of(st, trans), st->dt, s);
+  return check_launch();
+}
+
+// ------------------------------------------------------------------ FGMRES
+
+struct SolveInfo {
+  int its = 0, restarts = 0;
+  double rel = 0;
+};
+
+// Solve Acal k = f (padded planes). If use_guess, st->k holds the initial guess.
+int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s) {
+  const int m = st->opt.restart;
+  const long n = st->vlen;
+  double* sig = sigma_dev(st);
+  double* h = st->hres;
+  info = SolveInfo{};
+  // |f|
+  CHK(norm2(st, f, n, res_slot(st, 0), nullptr, s));
+  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double fnorm = std::sqrt(h[0]);
+  if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
+  if (fnorm == 0.0) {
+    HIPCHK(hipMemsetAsync(st->k, 0, n * sizeof(double), s));
+    return IRK_OK;
+  }
+  // initial residual into V_0
+  if (use_guess) {
+    CHK(apply_op(st, st->k, st->V, f, trans, s));
+  } else {
+    HIPCHK(hipMemsetAsync(st->k, 0, n * sizeof(double), s));
+    HIPCHK(hipMemcpyAsync(st->V, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  CHK(norm2(st, st->V, n, res_slot(st, 0), sig, s));
+  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double beta = std::sqrt(h[0]);
+  const double target = st->opt.rtol * fnorm;
+  if (beta <= target) {
+    info.rel = beta / fnorm;
+    return IRK_OK;
+  }
+  const bool selective = st->opt.orth == IRK_ORTH_CGS_SELECTIVE;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), sig_h(m + 1), y(m);
+  while (true) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    sig_h[0] = 1.0 / beta;
+    int jdone = 0;
+    bool converged_est = false;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = st->V + (long)j * n;
+      double* Vn = st->V + (long)(j + 1) * n;
+      double* Zj = st->Z + (long)j * n;
+      CHK(precondition(st, Vj, sig_h[j], Zj, trans, s));
+      CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
+      // pass A: h = V^T w, |w|^2
+      OrthoArgs a = ortho_base();
+      a.V = st->V;
+      a.vstride = n;
+      a.nv = j + 1;
+      a.w = Vn;
+      a.len = n;
+      a.vscale = sig;
+      a.want_dots = 1;
+      a.result = res_slot(st, 0);
+      CHK(ortho(st, a, s));
+      // pass B: w -= V h; h2 = V^T w; |w|^2; flag = |w|^2 < eta^2 |w_before|^2
+      OrthoArgs b = a;
+      b.coef = res_slot(st, 0);
+      b.result = res_slot(st, 1);
+      b.sigma_out = sig + (j + 1);
+      b.flag_out = st->dflag;
+      b.ref = res_slot(st, 0) + (j + 1);
+      b.eta2 = 0.5;
+      CHK(ortho(st, b, s));
+      // pass C: w -= V h2; |w|^2 (skipped unless needed for the selective variant)
+      OrthoArgs c = a;
+      c.coef = res_slot(st, 1);
+      c.want_dots = 0;
+      c.result = res_slot(st, 2);
+      c.sigma_out = sig + (j + 1);
+      c.skip = selective ? st->dflag : nullptr;
+      CHK(ortho(st, c, s));
+      HIPCHK(hipMemcpyAsync(h, st->dres, 3L * RSTRIDE * sizeof(double), hipMemcpyDeviceToHost, s));
+      int flag = 1;
+      if (selective) HIPCHK(hipMemcpyAsync(&flag, st->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const bool reorth = !selective || flag != 0;
+      const double* rA = h;
+      const double* rB = h + RSTRIDE;
+      const double* rC = h + 2 * RSTRIDE;
+      double* col = &H[(size_t)j];  // column j, row stride m
+      for (int i = 0; i <= j; ++i) col[(size_t)i * m] = rA[i] + (reorth ? rB[i] : 0.0);
+      const double hn = std::sqrt(reorth ? rC[j + 1] : rB[j + 1]);
+      bool finite = std::isfinite(hn);
+      for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(col[(size_t)i * m]);
+      if (!finite) return fail(IRK_EBREAKDOWN, "non-finite Hessenberg entry in FGMRES");
+      sig_h[j + 1] = 1.0 / hn;
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        const double t0 = cs[i] * col[(size_t)i * m] + sn[i] * col[(size_t)(i + 1) * m];
+        const double t1 = -sn[i] * col[(size_t)i * m] + cs[i] * col[(size_t)(i + 1) * m];
+        col[(size_t)i * m] = t0;
+        col[(size_t)(i + 1) * m] = t1;
+      }
+      const double hj = col[(size_t)j * m];
+      const double r = std::hypot(hj, hn);
+      cs[j] = hj / r;
+      sn[j] = hn / r;
+      col[(size_t)j * m] = r;
+      col[(size_t)(j + 1) * m] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      info.its++;
+      jdone = j + 1;
+      if (std::fabs(gv[j + 1]) <= target || hn <= 1e-300 * std::max(1.0, r)) {
+        converged_est = true;
+        break;
+      }
+      if (info.its >= st->opt.max_it) break;
+    }
+    // y = R^{-1} g
+    for (int i = jdone - 1; i >= 0; --i) {
+      double v = gv[i];
+      for (int c2 = i + 1; c2 < jdone; ++c2) v -= H[(size_t)i * m + c2] * y[c2];
+      y[i] = v / H[(size_t)i * m + i];
+    }
+    // k += Z y
+    std::copy(y.begin(), y.begin() + jdone, h);
+    HIPCHK(hipMemcpyAsync(ycoef_dev(st), h, jdone * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+      OrthoArgs a = ortho_base();
+      a.V = st->Z;
+      a.vstride = n;
+      a.nv = jdone;
+      a.w = st->k;
+      a.len = n;
+      a.coef = ycoef_dev(st);
+      a.coef_sign = -1.0;
+      a.result = res_slot(st, 3);
+      CHK(ortho(st, a, s));
+    }
+    // true residual r = f - Acal k into V_0
+    CHK(apply_op(st, st->k, st->V, f, trans, s));
+    CHK(norm2(st, st->V, n, res_slot(st, 0), sig, s));
+    HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    beta = std::sqrt(h[0]);
+    info.rel = beta / fnorm;
+    if (!std::isfinite(beta)) return fail(IRK_EBREAKDOWN, "non-finite residual in FGMRES");
+    if (beta <= target) return IRK_OK;
+    if (info.its >= st->opt.max_it) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "FGMRES reached max_it = %d with relative residual %.3e > rtol %.3e", st->opt.max_it,
+               info.rel, st->opt.rtol);
+      return fail(IRK_ENOCONV, buf);
+    }
+    (void)converged_est;
+    info.restarts++;
+  }
+}
+
+void add_stats(irk_stats* stats, const SolveInfo& si) {
+  if (!stats) return;
+  stats->fgmres_its_total += si.its;
+  stats->fgmres_its_max = std::max(stats->fgmres_its_max, si.its);
+  stats->restarts_total += si.restarts;
+  stats->solves += 1;
+  stats->last_rel_resid = si.rel;
+}
+
+void init_stats(irk_stats* stats) {
+  if (!stats) return;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->failed_step = -1;
+}
+
+// one forward step on st->u (padded); stage derivatives left in st->k
+int forward_step(irk_stepper* st, const double* Fp, SolveInfo& si, hipStream_t s) {
+  launch_stage_rhs(st->u, Fp, st->f, st->prob->kappa, st->g, st->s, s);
+  const bool guess = st->opt.initial_guess == IRK_GUESS_PREV && st->have_prev;
+  CHK(fgmres(st, st->f, false, guess, si, s));
+  st->have_prev = true;
+  launch_update(st->u, st->k, st->s, b_of(st), st->dt, st->g, s);
+  return check_launch();
+}
+
+// ------------------------------------------------------------------ binomial checkpointing
+
+long binom_sat(long n, long k) {
+  if (k < 0 || k > n) return 0;
+  k = std::min(k, n - k);
+  double r = 1.0;
+  for (long i = 1; i <= k; ++i) {
+    r = r * (double)(n - k + i) / (double)i;
+    if (r > 4e18) return (long)4e18;
+  }
+  return (long)std::llround(r);
+}
+
+// minimal forward advances to reverse l steps with c slots (Griewank's binomial bound)
+long revolve_cost(long l, long c) {
+  if (l <= 1) return 0;
+  if (c <= 1) return l * (l - 1) / 2;
+  long r = 0;
+  while (binom_sat(c + r, c) < l) ++r;
+  return r * l - binom_sat(c + r, c + 1);
+}
+
+struct Action {
+  int kind, arg;
+};
+
+// reverse steps [a, a+l) with the state u_a in slot `slot`, `c` slots usable from `slot` on
+void revolve_rec(int a, int l, int c, int slot, int& cur, std::vector<Action>& out, long& adv) {
+  if (l <= 0) return;
+  if (l == 1) {
+    if (cur != a) out.push_back({2, slot});
+    cur = a;
+    out.push_back({3, a});
+    return;
+  }
+  if (c == 1) {
+    for (int stp = a + l - 1; stp >= a; --stp) {
+      if (cur != a) out.push_back({2, slot});
+      cur = a;
+      if (stp > a) {
+        out.push_back({0, stp - a});
+        adv += stp - a;
+        cur = stp;
+      }
+      out.push_back({3, stp});
+    }
+    return;
+  }
+  int best = 1;
+  long bestc = -1;
+  for (int k2 = 1; k2 < l; ++k2) {
+    const long cost = k2 + revolve_cost(l - k2, c - 1) + revolve_cost(k2, c);
+    if (bestc < 0 || cost < bestc) {
+      bestc = cost;
+      best = k2;
+    }
+  }
+  if (cur != a) out.push_back({2, slot});
+  out.push_back({0, best});
+  adv += best;
+  cur = a + best;
+  out.push_back({1, slot + 1});
+  revolve_rec(a + best, l - best, c - 1, slot + 1, cur, out, adv);
+  revolve_rec(a, best, c, slot, cur, out, adv);
+}
+
+std::vector<Action> revolve_schedule(int nsteps, int nsnap, long& adv) {
+  std::vector<Action> out;
+  adv = 0;
+  int cur = 0;
+  out.push_back({1, 0});
+  revolve_rec(0, nsteps, nsnap, 0, cur, out, adv);
+  return out;
+}
+
+int validate_stepper(const irk_stepper* st) {
+  if (!st) return fail(IRK_EINVAL, "stepper is NULL");
+  return IRK_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* irk_last_error(void) { return g_err.c_str(); }
+
+void irk_options_default(irk_options* o) {
+  if (!o) return;
+  o->precond = IRK_PC_GS_LOWER;
+  o->rtol = 1e-10;
+  o->restart = 30;
+  o->max_it = 300;
+  o->mg_coarse_n = 8;
+  o->cheb_degree = 2;
+  o->cheb_lo = 0.25;
+  o->cheb_hi = 1.1;
+  o->power_its = 15;
+  o->mg_precision = IRK_F64;
+  o->orth = IRK_ORTH_CGS2;
+  o->initial_guess = IRK_GUESS_ZERO;
+}
+
+int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stream) {
+  g_err.clear();
+  if (!out) return fail(IRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (N < 2 || N > 16384) return fail(IRK_EINVAL, "N must be in [2, 16384]");
+  if (!kappa) return fail(IRK_EINVAL, "kappa is NULL");
+  hipStream_t s = S(stream);
+  irk_problem* p = new irk_problem();
+  p->N = N;
+  p->g = make_geom(N);
+  const long kc = (long)N * p->g.pitch;
+  int rc = dev_alloc((void**)&p->kappa, kc * sizeof(double));
+  if (rc != IRK_OK) {
+    delete p;
+    return rc;
+  }
+  int* bad = nullptr;
+  rc = dev_alloc((void**)&bad, sizeof(int));
+  if (rc != IRK_OK) {
+    irk_problem_destroy(p);
+    return rc;
+  }
+  int hbad = 0;
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    launch_pack_elem(kappa, p->kappa, p->g, s);
+    launch_check_kappa(kappa, N * N, bad, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(bad);
+  if (e != hipSuccess) {
+    irk_problem_destroy(p);
+    return fail(IRK_EHIP, std::string("problem setup: ") + hipGetErrorString(e));
+  }
+  if (hbad) {
+    irk_problem_destroy(p);
+    return fail(IRK_EINVAL, "kappa must be finite and positive everywhere");
+  }
+  *out = p;
+  return IRK_OK;
+}
+
+void irk_problem_destroy(irk_problem* p) {
+  if (!p) return;
+  dev_free(p->kappa);
+  delete p;
+}
+
+int irk_apply_mass(const irk_problem* p, const double* x, double* y, void* stream) {
+  g_err.clear();
+  if (!p || !x || !y) return fail(IRK_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  double *xp = nullptr, *yp = nullptr;
+  CHK(dev_alloc((void**)&xp, 2 * p->g.plane * sizeof(double)));
+  yp = xp + p->g.plane;
+  launch_pack(x, xp, p->g, 1, s);
+  hipError_t e = hipMemsetAsync(yp, 0, p->g.plane * sizeof(double), s);
+  launch_mass(xp, yp, p->g, s);
+  launch_unpack(yp, y, p->g, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(xp);
+  if (e != hipSuccess) return fail(IRK_EHIP, hipGetErrorString(e));
+  return check_launch();
+}
+
+int irk_apply_stiffness(const irk_problem* p, const double* x, double* y, void* stream) {
+  g_err.clear();
+  if (!p || !x || !y) return fail(IRK_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  double* xp = nullptr;
+  CHK(dev_alloc((void**)&xp, 2 * p->g.plane * sizeof(double)));
+  double* yp = xp + p->g.plane;
+  launch_pack(x, xp, p->g, 1, s);
+  hipError_t e = hipMemsetAsync(yp, 0, p->g.plane * sizeof(double), s);
+  launch_stiff(xp, yp, p->kappa, p->g, s);
+  launch_unpack(yp, y, p->g, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(xp);
+  if (e != hipSuccess) return fail(IRK_EHIP, hipGetErrorString(e));
+  return check_launch();
+}
+
+void irk_stepper_destroy(irk_stepper* st) {
+  if (!st) return;
+  for (size_t l = 0; l < st->lv.size(); ++l) {
+    Level& L = st->lv[l];
+    if (L.kapc && L.kapc != L.kap64) dev_free(L.kapc);
+    if (L.own64) dev_free(L.kap64);
+    dev_free(L.t);
+    dev_free(L.x);
+    dev_free(L.e);
+  }
+  for (void* p : st->binv) dev_free(p);
+  dev_free(st->V);
+  dev_free(st->Z);
+  dev_free(st->f);
+  dev_free(st->k);
+  dev_free(st->kprev);
+  dev_free(st->tmp);
+  dev_free(st->tmp2);
+  dev_free(st->u);
+  dev_free(st->Fp);
+  dev_free(st->dres);
+  dev_free(st->dflag);
+  dev_free(st->rw.partial);
+  dev_free(st->rw.counter);
+  if (st->hres) (void)hipHostFree(st->hres);
+  delete st;
+}
+
+int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tableau* tab, double dt,
+                       const irk_options* opts, void* stream) {
+  g_err.clear();
+  if (!out) return fail(IRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p || !tab || !tab->A || !tab->b) return fail(IRK_EINVAL, "NULL problem or tableau");
+  if (tab->s < 1 || tab->s > kMaxStages) return fail(IRK_EINVAL, "tableau must have 1..8 stages");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(IRK_EINVAL, "dt must be finite and positive");
+  irk_options o;
+  irk_options_default(&o);
+  if (opts) o = *opts;
+  if (o.precond != IRK_PC_JACOBI && o.precond != IRK_PC_GS_LOWER) return fail(IRK_EINVAL, "unknown precond");
+  if (o.restart < 1 || o.restart > 32) return fail(IRK_EINVAL, "restart must be in 1..32");
+  if (o.max_it < 1) return fail(IRK_EINVAL, "max_it must be >= 1");
+  if (!(o.rtol > 0) || !(o.rtol < 1)) return fail(IRK_EINVAL, "rtol must be in (0, 1)");
+  if (o.cheb_degree < 1 || o.cheb_degree > kMaxDeg) return fail(IRK_EINVAL, "cheb_degree must be 1..3");
+  if (!(o.cheb_lo > 0) || !(o.cheb_hi > o.cheb_lo)) return fail(IRK_EINVAL, "need 0 < cheb_lo < cheb_hi");
+  if (o.power_its < 1 || o.power_its > 1000) return fail(IRK_EINVAL, "power_its must be 1..1000");
+  if (o.mg_precision < IRK_F64 || o.mg_precision > IRK_BF16) return fail(IRK_EINVAL, "unknown mg_precision");
+  if (o.orth != IRK_ORTH_CGS2 && o.orth != IRK_ORTH_CGS_SELECTIVE) return fail(IRK_EINVAL, "unknown orth");
+  if (o.initial_guess != IRK_GUESS_ZERO && o.initial_guess != IRK_GUESS_PREV)
+    return fail(IRK_EINVAL, "unknown initial_guess");
+  if (o.mg_coarse_n < 2) return fail(IRK_EINVAL, "mg_coarse_n must be >= 2");
+  const int s = tab->s;
+  for (int i = 0; i < s * s; ++i)
+    if (!std::isfinite(tab->A[i])) return fail(IRK_EINVAL, "non-finite tableau entry");
+  for (int i = 0; i < s; ++i) {
+    if (!std::isfinite(tab->b[i])) return fail(IRK_EINVAL, "non-finite tableau entry");
+    if (!(tab->A[i * s + i] > 0))
+      return fail(IRK_EINVAL, "every diagonal entry a_ii must be > 0 (the diagonal blocks M + dt*a_ii*K must be SPD)");
+  }
+  if (p->N < 2) return fail(IRK_EINVAL, "bad problem");
+  irk_stepper* st = new irk_stepper();
+  st->prob = p;
+  st->s = s;
+  for (int i = 0; i < s * s; ++i) st->A[i] = tab->A[i];
+  for (int i = 0; i < s; ++i) {
+    st->b[i] = tab->b[i];
+    st->c[i] = tab->c ? tab->c[i] : 0.0;
+  }
+  st->dt = dt;
+  st->opt = o;
+  st->prec = o.mg_precision;
+  st->g = p->g;
+  st->vlen = (long)s * p->g.plane;
+  hipStream_t hs = S(stream);
+  const int m = o.restart;
+  const size_t vb = st->vlen * sizeof(double);
+  int rc = IRK_OK;
+  auto alloc_zero = [&](double** ptr, size_t bytes) {
+    if (rc != IRK_OK) return;
+    rc = dev_alloc((void**)ptr, bytes);
+    if (rc == IRK_OK && hipMemsetAsync(*ptr, 0, bytes, hs) != hipSuccess) rc = fail(IRK_EHIP, "memset failed");
+  };
+  alloc_zero(&st->V, vb * (m + 1));
+  alloc_zero(&st->Z, vb * m);
+  alloc_zero(&st->f, vb);
+  alloc_zero(&st->k, vb);
+  alloc_zero(&st->kprev, vb);
+  // scratch planes; at least two, the power iteration keeps x and y in tmp
+  const size_t tb = (size_t)std::max(s, 2) * p->g.plane * sizeof(double);
+  alloc_zero(&st->tmp, tb);
+  alloc_zero(&st->tmp2, tb);
+  alloc_zero(&st->u, p->g.plane * sizeof(double));
+  alloc_zero(&st->Fp, p->g.plane * sizeof(double));
+  alloc_zero(&st->dres, DRES_LEN * sizeof(double));
+  if (rc == IRK_OK) rc = dev_alloc((void**)&st->dflag, sizeof(int));
+  st->rw.max_blocks = 1024;
+  alloc_zero(&st->rw.partial, (size_t)st->rw.max_blocks * (kMaxRestart + 1) * sizeof(double));
+  if (rc == IRK_OK) {
+    rc = dev_alloc((void**)&st->rw.counter, 64);
+    if (rc == IRK_OK && hipMemsetAsync(st->rw.counter, 0, 64, hs) != hipSuccess) rc = fail(IRK_EHIP, "memset");
+  }
+  if (rc == IRK_OK && hipHostMalloc((void**)&st->hres, DRES_LEN * sizeof(double)) != hipSuccess)
+    rc = fail(IRK_ENOMEM, "hipHostMalloc failed");
+  if (rc == IRK_OK) rc = setup_multigrid(st, hs);
+  if (rc == IRK_OK && hipStreamSynchronize(hs) != hipSuccess) rc = fail(IRK_EHIP, "setup synchronisation failed");
+  if (rc != IRK_OK) {
+    std::string keep = g_err;
+    irk_stepper_destroy(st);
+    g_err = keep;
+    return rc;
+  }
+  *out = st;
+  return IRK_OK;
+}
+
+int irk_stepper_sizes(const irk_stepper* st, int* N, int* s, int* levels) {
+  CHK(validate_stepper(st));
+  if (N) *N = st->prob->N;
+  if (s) *s = st->s;
+  if (levels) *levels = (int)st->lv.size();
+  return IRK_OK;
+}
+
+int irk_stepper_mu(const irk_stepper* st, int stage, int level, double* mu) {
+  CHK(validate_stepper(st));
+  const int L = (int)st->lv.size();
+  if (stage < 0 || stage >= st->s || level < 0 || level >= L || !mu) return fail(IRK_EINVAL, "bad stage/level");
+  *mu = st->mu[(size_t)stage * L + level];
+  return IRK_OK;
+}
+
+int irk_stage_rhs(const irk_stepper* cst, const double* u, const double* F, double* f, void* stream) {
+  g_err.clear();
+  CHK(validate_stepper(cst));
+  if (!u || !f) return fail(IRK_EINVAL, "NULL argument");
+  irk_stepper* st = const_cast<irk_stepper*>(cst);
+  hipStream_t s = S(stream);
+  launch_pack(u, st->u, st->g, 1, s);
+  if (F) launch_pack(F, st->Fp, st->g, 1, s);
+  launch_stage_rhs(st->u, F ? st->Fp : nullptr, st->f, st->prob->kappa, st->g, st->s, s);
+  launch_unpack(st->f, f, st->g, st->s, s);
+  return check_launch();
+}
+
+int irk_apply_stage_operator(const irk_stepper* cst, const double* x, double* y, int transpose, void* stream) {
+  g_err.clear();
+  CHK(validate_stepper(cst));
+  if (!x || !y) return fail(IRK_EINVAL, "NULL argument");
+  irk_stepper* st = const_cast<irk_stepper*>(cst);
+  hipStream_t s = S(stream);
+  launch_pack(x, st->tmp, st->g, st->s, s);
+  CHK(apply_op(st, st->tmp, st->f, nullptr, transpose != 0, s));
+  launch_unpack(st->f, y, st->g, st->s, s);
+  return check_launch();
+}
+
+int irk_apply_preconditioner(const irk_stepper* cst, const double* v, double* z, int transpose, void* stream) {
+  g_err.clear();
+  CHK(validate_stepper(cst));
+  if (!v || !z) return fail(IRK_EINVAL, "NULL argument");
+  irk_stepper* st = const_cast<irk_stepper*>(cst);
+  hipStream_t s = S(stream);
+  launch_pack(v, st->f, st->g, st->s, s);
+  CHK(precondition(st, st->f, 1.0, st->k, transpose != 0, s));
+  launch_unpack(st->k, z, st->g, st->s, s);
+  return check_launch();
+}
+
+int irk_vcycle(const irk_stepper* cst, int stage, const double* t, double* z, void* stream) {
+  g_err.clear();
+  CHK(validate_stepper(cst));
+  if (!t || !z) return fail(IRK_EINVAL, "NULL argument");
+  if (stage < 0 || stage >= cst->s) return fail(IRK_EINVAL, "stage out of range");
+  irk_stepper* st = const_cast<irk_stepper*>(cst);
+  hipStream_t s = S(stream);
+  launch_pack(t, st->f, st->g, 1, s);
+  CHK(vcycle(st, stage, st->f, 1.0, st->k, s));
+  launch_unpack(st->k, z, st->g, 1, s);
+  return check_launch();
+}
+
+int irk_solve_stages(irk_stepper* st, const double* f, double* k, int transpose, irk_stats* stats, void* stream) {
+  g_err.clear();
+  init_stats(stats);
+  CHK(validate_stepper(st));
+  if (!f || !k) return fail(IRK_EINVAL, "NULL argument");
+  hipStream_t s = S(stream);
+  launch_pack(f, st->f, st->g, st->s, s);
+  CHK(check_launch());
+  SolveInfo si;
+  const int rc = fgmres(st, st->f, transpose != 0, false, si, s);
+  add_stats(stats, si);
+  if (rc != IRK_OK) {
+    if (stats) stats->failed_step = 0;
+    return rc;
+  }
+  launch_unpack(st->k, k, st->g, st->s, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return check_launch();
+}
+
+int irk_advance(irk_stepper* st, double* u, const double* F, int nsteps, irk_stats* stats, void* stream) {
+  g_err.clear();
+  init_stats(stats);
+  CHK(validate_stepper(st));
+  if (!u) return fail(IRK_EINVAL, "u is NULL");
+  if (nsteps < 0) return fail(IRK_EINVAL, "nsteps must be >= 0");
+  hipStream_t s = S(stream);
+  launch_pack(u, st->u, st->g, 1, s);
+  if (F) launch_pack(F, st->Fp, st->g, 1, s);
+  CHK(check_launch());
+  st->have_prev = false;
+  for (int n = 0; n < nsteps; ++n) {
+    SolveInfo si;
+    const int rc = forward_step(st, F ? st->Fp : nullptr, si, s);
+    add_stats(stats, si);
+    if (rc != IRK_OK) {
+      // the update only runs after a converged solve: st->u is the last good state
+      if (stats) stats->failed_step = n;
+      std::string keep = g_err;
+      launch_unpack(st->u, u, st->g, 1, s);
+      (void)hipStreamSynchronize(s);
+      g_err = keep;
+      return rc;
+    }
+    if (stats) stats->steps_done = n + 1;
+  }
+  launch_unpack(st->u, u, st->g, 1, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return check_launch();
+}
+
+int irk_revolve_schedule(int nsteps, int nsnap, int* actions, int cap, int* count, int* advances) {
+  g_err.clear();
+  if (nsteps < 0 || nsnap < 1) return fail(IRK_EINVAL, "need nsteps >= 0 and nsnap >= 1");
+  long adv = 0;
+  std::vector<Action> sch = revolve_schedule(nsteps, std::min(nsnap, std::max(nsteps, 1)), adv);
+  if (count) *count = (int)sch.size();
+  if (advances) *advances = (int)adv;
+  if (!actions) return IRK_OK;
+  if ((int)sch.size() > cap) return fail(IRK_EINVAL, "action buffer too small");
+  for (size_t i = 0; i < sch.size(); ++i) {
+    actions[2 * i] = sch[i].kind;
+    actions[2 * i + 1] = sch[i].arg;
+  }
+  return IRK_OK;
+}
+
+int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const double* lambda_T, double* lambda_0,
+                double* grad_logkappa, irk_stats* stats, void* stream) {
+  g_err.clear();
+  init_stats(stats);
+  CHK(validate_stepper(st));
+  if (!u0 || !lambda_T) return fail(IRK_EINVAL, "NULL argument");
+  if (nsteps < 0 || nsnap < 1) return fail(IRK_EINVAL, "need nsteps >= 0 and nsnap >= 1");
+  hipStream_t s = S(stream);
+  const Geom& g = st->g;
+  const int slots = std::min(nsnap, std::max(nsteps, 1));
+  double* snaps = nullptr;
+  double* lam = nullptr;
+  double* grad = nullptr;
+  double* nu = nullptr;
+  double* kstep = nullptr;
+  const long gcount = (long)g.N * g.pitch;
+  int rc = dev_alloc((void**)&snaps, (size_t)slots * g.plane * sizeof(double));
+  if (rc == IRK_OK) rc = dev_alloc((void**)&lam, g.plane * sizeof(double));
+  if (rc == IRK_OK) rc = dev_alloc((void**)&grad, gcount * sizeof(double));
+  if (rc == IRK_OK) rc = dev_alloc((void**)&nu, st->vlen * sizeof(double));
+  if (rc == IRK_OK) rc = dev_alloc((void**)&kstep, st->vlen * sizeof(double));
+  auto cleanup = [&]() {
+    dev_free(snaps);
+    dev_free(lam);
+    dev_free(grad);
+    dev_free(nu);
+    dev_free(kstep);
+  };
+  if (rc != IRK_OK) {
+    cleanup();
+    return rc;
+  }
+  if (hipMemsetAsync(grad, 0, gcount * sizeof(double), s) != hipSuccess) rc = fail(IRK_EHIP, "memset");
+  launch_pack(u0, st->u, g, 1, s);
+  launch_pack(lambda_T, lam, g, 1, s);
+  long adv = 0;
+  std::vector<Action> sch = revolve_schedule(nsteps, slots, adv);
+  const Coefs at = coefs_of(st, false);
+  const Coefs bb = b_of(st);
+  st->have_prev = false;
+  int done = 0;
+  for (size_t q = 0; q < sch.size() && rc == IRK_OK; ++q) {
+    const Action& act = sch[q];
+    if (act.kind == 0) {
+      for (int r = 0; r < act.arg && rc == IRK_OK; ++r) {
+        SolveInfo si;
+        rc = forward_step(st, nullptr, si, s);
+        add_stats(stats, si);
+      }
+    } else if (act.kind == 1) {
+      if (hipMemcpyAsync(snaps + (long)act.arg * g.plane, st->u, g.plane * sizeof(double), hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+        rc = fail(IRK_EHIP, "snapshot copy failed");
+    } else if (act.kind == 2) {
+      if (hipMemcpyAsync(st->u, snaps + (long)act.arg * g.plane, g.plane * sizeof(double), hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+        rc = fail(IRK_EHIP, "snapshot copy failed");
+    } else {
+      // reverse step act.arg from u_n = st->u: recompute its stages, then the adjoint step
+      SolveInfo si;
+      launch_stage_rhs(st->u, nullptr, st->f, st->prob->kappa, g, st->s, s);
+      rc = fgmres(st, st->f, false, false, si, s);
+      add_stats(stats, si);
+      if (rc != IRK_OK) break;
+      if (hipMemcpyAsync(kstep, st->k, st->vlen * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        rc = fail(IRK_EHIP, "copy failed");
+        break;
+      }
+      launch_adjoint_rhs(lam, st->f, st->s, bb, st->dt, g, s);
+      SolveInfo sa;
+      rc = fgmres(st, st->f, true, false, sa, s);
+      add_stats(stats, sa);
+      if (rc != IRK_OK) break;
+      if (hipMemcpyAsync(nu, st->k, st->vlen * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        rc = fail(IRK_EHIP, "copy failed");
+        break;
+      }
+      launch_kappa_grad(grad, st->u, kstep, nu, st->prob->kappa, g, st->s, at, st->dt, s);
+      launch_lambda_update(lam, nu, st->s, st->prob->kappa, g, s);
+      rc = check_launch();
+      ++done;
+    }
+  }
+  if (rc == IRK_OK) {
+    if (lambda_0) launch_unpack(lam, lambda_0, g, 1, s);
+    if (grad_logkappa) launch_unpack_elem(grad, grad_logkappa, g, s);
+    rc = check_launch();
+    if (rc == IRK_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(IRK_EHIP, "synchronisation failed");
+  } else {
+    std::string keep = g_err;
+    (void)hipStreamSynchronize(s);
+    g_err = keep;
+  }
+  if (stats) {
+    stats->forward_advances = (int)adv;
+    stats->steps_done = done;
+    if (rc != IRK_OK) stats->failed_step = nsteps - 1 - done;
+  }
+  cleanup();
+  return rc;
+}
+
+}  // extern "C"

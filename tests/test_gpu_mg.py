@@ -1,0 +1,71 @@
+"""GPU parity: multigrid V-cycle (a4) and block stage preconditioners (a3) vs the oracle's CSR statement."""
+import numpy as np
+import pytest
+
+from oracle import fem, mg
+from oracle import tableaux as OT
+import paper_2403_08084_amd as P
+import synth
+from gpu_util import dev, host, make, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("N,dt,deg", [(64, 1e-3, 2), (96, 1e-3, 2), (128, 5e-4, 2), (32, 1.0 / 32, 2), (64, 1e-3, 1),
+                                      (64, 1e-3, 3), (8, 1e-3, 2)])
+def test_vcycle_fp64_matches_oracle(N, dt, deg):
+    kap = synth.grf_kappa(N, 1)
+    otab = OT.radau_iia(3)
+    hier = mg.Hierarchy(N, kap, dt, cheb_degree=deg)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, cheb_degree=deg)
+    assert stp.levels == len(hier.sizes)
+    t = np.random.default_rng(7).standard_normal((N - 1) ** 2)
+    for i in range(3):
+        a = otab["A"][i, i]
+        _, _, mus, _ = hier.block(a)
+        for l in range(len(hier.sizes) - 1):
+            assert abs(stp.mu(i, l) - mus[l]) <= 1e-11 * mus[l]
+        z = host(stp.vcycle(i, dev(t)))
+        assert rel(z, hier.vcycle(a, t)) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(P.F32, 2e-5), (P.BF16, 3e-2)])
+def test_vcycle_reduced_precision(prec, tol):
+    N, dt = 128, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    hier = mg.Hierarchy(N, kap, dt)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, mg_precision=prec)
+    t = np.random.default_rng(8).standard_normal((N - 1) ** 2)
+    a = OT.radau_iia(3)["A"][1, 1]
+    z = host(stp.vcycle(1, dev(t)))
+    assert rel(z, hier.vcycle(a, t)) < tol
+
+
+def test_vcycle_contracts():
+    N, dt = 256, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt)
+    a = OT.radau_iia(3)["A"][0, 0]
+    B = (M + dt * a * K).tocsr()
+    e = np.random.default_rng(9).standard_normal((N - 1) ** 2)
+    for _ in range(3):
+        e2 = e - host(stp.vcycle(0, dev(B @ e)))
+        assert np.linalg.norm(e2) < 0.2 * np.linalg.norm(e)
+        e = e2
+
+
+@pytest.mark.parametrize("kind,pc", [("jacobi", P.PC_JACOBI), ("gs_lower", P.PC_GS_LOWER)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_block_preconditioner(kind, pc, transpose):
+    N, dt = 96, 1e-3
+    kap = synth.grf_kappa(N, 3)
+    M, K = fem.assemble(N, kap)
+    otab = OT.radau_iia(3)
+    A = otab["A"].T if transpose else otab["A"]
+    hier = mg.Hierarchy(N, kap, dt)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=pc)
+    v = synth.random_stage_block(N, 3, 11).ravel()
+    z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
+    ref = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.vcycle_block_solver(hier, A))
+    assert rel(z, ref) < 1e-12

@@ -1,0 +1,177 @@
+"""GPU parity: FGMRES stage solve (a5), time stepping (a1+a5+a6) and the mixed-precision form (a7)
+against the oracle's exact direct solves and closed forms."""
+import numpy as np
+import pytest
+
+from oracle import fem, step
+from oracle import tableaux as OT
+import paper_2403_08084_amd as P
+import synth
+from gpu_util import dev, host, make, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _max_rel(gpu_list, ora_list):
+    return max(rel(a, b) for a, b in zip(gpu_list, ora_list))
+
+
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_solve_stages_matches_direct(pc, transpose):
+    N, dt = 64, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    otab = OT.radau_iia(3)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=pc, rtol=1e-12)
+    f = synth.random_stage_block(N, 3, 21).ravel()
+    k, stats = stp.solve_stages(dev(f), transpose=transpose)
+    ref = step.CoupledLU(M, K, otab["A"], dt).solve(f, trans=transpose)
+    Acal = step.coupled_matrix(M, K, otab["A"].T if transpose else otab["A"], dt)
+    assert np.linalg.norm(Acal @ host(k) - f) <= 1.01e-12 * np.linalg.norm(f)
+    assert stats["last_rel_resid"] <= 1e-12
+    assert rel(host(k), ref) < 1e-9
+    assert stats["fgmres_its_total"] > 1
+
+
+def test_config1_decay():
+    # 32x32, Radau IIA(2), dt = 1/32, 10 steps, u0 = sin(pi x) sin(pi y)
+    N, dt = 32, 1.0 / 32
+    u0 = synth.sine_mode_vector(N, 1, 1)
+    _, stp = make(N, np.ones(N * N), P.tableaux.radau_iia(2), dt, rtol=1e-13)
+    u = dev(u0)
+    gpu = [u0.copy()]
+    for _ in range(10):
+        stp.advance(u, 1)
+        gpu.append(host(u))
+    ora = step.run(N, None, OT.radau_iia(2), dt, 10, u0)
+    lam = step.discrete_eigenvalue(N, 1, 1)
+    R = OT.stability_function(OT.radau_iia(2), -dt * lam)[0].real
+    assert _max_rel(gpu, ora) < 1e-10
+    assert rel(gpu[-1], R**10 * u0) < 1e-10
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_config2_shape_closed_form(N):
+    # Radau IIA(3), dt = 1e-3, 16 seeded sine modes, kappa = 1, P_L + FP64 V-cycle: closed form R(-dt lam)^n
+    dt, nsteps = 1e-3, 10
+    u0, amps = synth.sine_modes_u0(N, 0)
+    _, stp = make(N, np.ones(N * N), P.tableaux.radau_iia(3), dt, rtol=1e-12)
+    u = dev(u0)
+    gpu = []
+    for _ in range(nsteps):
+        _, st = stp.advance(u, 1)
+        gpu.append(host(u))
+    cf = step.closed_form_modes(N, OT.radau_iia(3), dt, nsteps, amps)[1:]
+    assert _max_rel(gpu, cf) < 1e-10
+
+
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
+def test_config3_shape_gl4(pc):
+    # variable kappa (GRF), Gauss-Legendre(4), dt = 5e-4; direct coupled oracle
+    N, dt, nsteps = 128, 5e-4, 4
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    _, stp = make(N, kap, P.tableaux.gauss_legendre(4), dt, precond=pc, rtol=1e-12)
+    u = dev(u0)
+    gpu = []
+    its = 0
+    for _ in range(nsteps):
+        _, st = stp.advance(u, 1)
+        its += st["fgmres_its_total"]
+        gpu.append(host(u))
+    ora = step.run(N, kap, OT.gauss_legendre(4), dt, nsteps, u0)[1:]
+    assert _max_rel(gpu, ora) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(P.F64, 1e-10), (P.F32, 1e-8), (P.BF16, 1e-8)])
+def test_config4_shape_mixed_precision(prec, tol):
+    # Radau IIA(3), dt = 1e-3, GRF kappa; multigrid in FP64 / FP32 / BF16 storage, outer FGMRES FP64 at rtol 1e-10
+    N, dt, nsteps = 128, 1e-3, 5
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, mg_precision=prec, rtol=1e-10)
+    u = dev(u0)
+    gpu = []
+    for _ in range(nsteps):
+        stp.advance(u, 1)
+        gpu.append(host(u))
+    ora = step.run(N, kap, OT.radau_iia(3), dt, nsteps, u0)[1:]
+    assert _max_rel(gpu, ora) < tol
+
+
+def test_selective_reorthogonalisation_and_prev_guess():
+    N, dt, nsteps = 64, 1e-3, 4
+    kap = synth.grf_kappa(N, 2)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    ora = step.run(N, kap, OT.radau_iia(3), dt, nsteps, u0)[-1]
+    for opts in ({"orth": P.ORTH_CGS_SELECTIVE}, {"initial_guess": P.GUESS_PREV}):
+        _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, rtol=1e-12, **opts)
+        u = dev(u0)
+        stp.advance(u, nsteps)
+        assert rel(host(u), ora) < 1e-10
+
+
+def test_dirk_gs_lower_with_exact_blocks_converges_in_one_iteration():
+    # lower-triangular A: P_L equals the stage operator; with one level the V-cycle is an exact solve
+    N, dt = 8, 1e-2
+    kap = synth.grf_kappa(N, 3)
+    _, stp = make(N, kap, P.tableaux.alexander(), dt, precond=P.PC_GS_LOWER, rtol=1e-12)
+    assert stp.levels == 1
+    f = synth.random_stage_block(N, 3, 2).ravel()
+    _, stats = stp.solve_stages(dev(f))
+    assert stats["fgmres_its_total"] == 1
+    # s = 1 (backward Euler) with P_D likewise
+    _, stp1 = make(N, kap, P.tableaux.radau_iia(1), dt, precond=P.PC_JACOBI, rtol=1e-12)
+    _, stats = stp1.solve_stages(dev(f[: (N - 1) ** 2]))
+    assert stats["fgmres_its_total"] == 1
+
+
+def test_iterations_grow_with_stages_and_gs_beats_jacobi():
+    # paper's trend (Section 4.1 heat study): P_D and P_L iteration counts grow with s; P_L needs fewer than P_D
+    N, dt = 128, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    its = {}
+    for pc in (P.PC_JACOBI, P.PC_GS_LOWER):
+        for s in (1, 2, 3):
+            _, stp = make(N, kap, P.tableaux.radau_iia(s), dt, precond=pc, rtol=1e-10)
+            u = dev(u0)
+            _, st = stp.advance(u, 2)
+            its[(pc, s)] = st["fgmres_its_total"] / 2
+    assert its[(P.PC_JACOBI, 3)] > its[(P.PC_JACOBI, 1)]
+    assert its[(P.PC_GS_LOWER, 3)] > its[(P.PC_GS_LOWER, 1)]
+    assert its[(P.PC_GS_LOWER, 3)] < its[(P.PC_JACOBI, 3)]
+
+
+def test_enoconv_keeps_last_good_state():
+    N, dt = 64, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, rtol=1e-14, max_it=1)
+    u = dev(u0)
+    rc, st = stp.advance(u, 3, check=False)
+    assert rc == P.IRK_ENOCONV
+    assert st["failed_step"] == 0 and st["steps_done"] == 0
+    assert np.array_equal(host(u), u0)
+
+
+def test_invalid_kappa_rejected():
+    N = 16
+    kap = np.ones(N * N)
+    kap[5] = np.nan
+    with pytest.raises(P.IrkError) as e:
+        P.Problem(N, dev(kap))
+    assert e.value.code == P.IRK_EINVAL
+    kap[5] = -1.0
+    with pytest.raises(P.IrkError):
+        P.Problem(N, dev(kap))
+
+
+def test_invalid_tableau_rejected():
+    N = 16
+    prob = P.Problem(N, dev(np.ones(N * N)))
+    explicit = {"A": np.array([[0.0, 0.0], [1.0, 0.0]]), "b": np.array([0.5, 0.5]), "c": np.array([0.0, 1.0])}
+    with pytest.raises(P.IrkError) as e:
+        P.Stepper(prob, explicit, 1e-3)
+    assert e.value.code == P.IRK_EINVAL
