@@ -37,11 +37,23 @@ def parse():
     ap.add_argument("--precision", choices=["f32", "bf16", "f64"], default="f32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precond", choices=["gs", "jacobi"], default="gs")
+    ap.add_argument("--orth", choices=["cgs2", "selective"], default="cgs2")
+    ap.add_argument("--guess", choices=["zero", "prev"], default="zero")
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--coarse-n", type=int, default=32)
     return ap.parse_args()
 
 
-def timed_run(P, torch, prob, tab, dt, u0_dev, steps, warmup, prec):
-    stp = P.Stepper(prob, tab, dt, mg_precision=prec, precond=P.PC_GS_LOWER, restart=30, rtol=1e-10)
+def solver_options(P, args):
+    return dict(precond={"gs": P.PC_GS_LOWER, "jacobi": P.PC_JACOBI}[args.precond],
+                orth={"cgs2": P.ORTH_CGS2, "selective": P.ORTH_CGS_SELECTIVE}[args.orth],
+                initial_guess={"zero": P.GUESS_ZERO, "prev": P.GUESS_PREV}[args.guess],
+                restart=args.restart, mg_coarse_n=args.coarse_n, rtol=1e-10)
+
+
+def timed_run(P, torch, prob, tab, dt, u0_dev, steps, warmup, prec, opts):
+    stp = P.Stepper(prob, tab, dt, mg_precision=prec, **opts)
     if warmup > 0:
         uw = u0_dev.clone()
         stp.advance(uw, warmup)
@@ -80,7 +92,8 @@ def main():
     tab = P.tableaux.radau_iia(3)
     u0d = torch.as_tensor(u0).cuda()
     prec = {"f32": P.F32, "bf16": P.BF16, "f64": P.F64}[args.precision]
-    stp, u, ms, stats = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, prec)
+    opts = solver_options(P, args)
+    stp, u, ms, stats = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, prec, opts)
     value = n * s * args.steps / (ms / 1e3)
     out = {
         "metric": METRIC,
@@ -99,9 +112,11 @@ def main():
                                f"FGMRES(30) rtol 1e-10, P_L + 1 GMG V-cycle Cheb(2), MG {args.precision}",
                    "N": N, "dofs": n, "stages": s, "global_batch": 1, "seq_len": 0, "parallelism": "none"},
         "fgmres_its_per_step": stats["fgmres_its_total"] / max(1, args.steps),
+        "solver": {"precond": args.precond, "orth": args.orth, "guess": args.guess, "restart": args.restart,
+                   "coarse_n": args.coarse_n},
     }
     if not args.no_fp64 and prec != P.F64:
-        _, u64, ms64, st64 = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, P.F64)
+        _, u64, ms64, st64 = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, P.F64, opts)
         out["fp64"] = {"value": n * s * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                        "fgmres_its_per_step": st64["fgmres_its_total"] / max(1, args.steps)}
         out["mixed_over_fp64"] = value / out["fp64"]["value"]

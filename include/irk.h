@@ -76,7 +76,7 @@ typedef struct {
   double rtol;        /* stop when |f - Acal k|_2 <= rtol * |f|_2 (true residual)  */
   int restart;        /* FGMRES restart length m, 1..32                           */
   int max_it;         /* total FGMRES iterations allowed per stage solve          */
-  int mg_coarse_n;    /* coarsening stops before a level below this many elements */
+  int mg_coarse_n;    /* coarsen while a level has an even element count > this  */
   int cheb_degree;    /* Chebyshev smoothing degree, 1..3                          */
   double cheb_lo;     /* smoothing interval [cheb_lo*mu, cheb_hi*mu]              */
   double cheb_hi;
@@ -84,6 +84,8 @@ typedef struct {
   int mg_precision;   /* IRK_F64, IRK_F32 or IRK_BF16 (storage; BF16 computes in FP32) */
   int orth;           /* IRK_ORTH_CGS2 or IRK_ORTH_CGS_SELECTIVE                  */
   int initial_guess;  /* IRK_GUESS_ZERO or IRK_GUESS_PREV (previous step's k)     */
+  int use_graphs;     /* 1: replay each Krylov iteration as a captured HIP graph;  
+                         0: launch every kernel eagerly (same arithmetic)          */
 } irk_options;
 
 /* Per-call statistics (host struct, filled if non-NULL). */
@@ -104,15 +106,16 @@ typedef struct irk_stepper irk_stepper;
 /* Message for the last error on the calling thread ("" if none). */
 const char *irk_last_error(void);
 
-/* Defaults: GS_LOWER, rtol 1e-10, restart 30, max_it 300, coarse 8, Chebyshev
+/* Defaults: GS_LOWER, rtol 1e-10, restart 30, max_it 300, coarse 32, Chebyshev
  * degree 2 on [0.25 mu, 1.1 mu] (the interval of Section 4.3), 15 power
- * iterations, FP64 multigrid, CGS2, zero initial guess. */
+ * iterations, FP64 multigrid, CGS2, zero initial guess, graphs on. */
 void irk_options_default(irk_options *opts);
 
 /* Problem: the grid and the diffusivity. N >= 2 elements per side; kappa is a
  * device array of N*N doubles (element layout), copied; every entry must be
- * finite and > 0 (IRK_EINVAL otherwise). The multigrid needs N = Nc * 2^L with
- * (Nc-1)^2 <= 1024; other N are accepted for the operators alone. */
+ * finite and > 0 (IRK_EINVAL otherwise). The multigrid halves N while it is even
+ * and above mg_coarse_n; the coarsest level Nc needs (Nc-1)^2 <= 1024 (dense solve),
+ * otherwise stepper creation fails with IRK_EINVAL. */
 int irk_problem_create(irk_problem **out, int N, const double *kappa, void *stream);
 void irk_problem_destroy(irk_problem *p);
 

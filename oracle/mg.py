@@ -17,9 +17,9 @@ of Section 3.1, there written a_jj^{-1} M + dt K for the IA form). The paper
 approximates B_i^{-1} by multigrid; this module states the geometric multigrid
 V-cycle used for that:
 
-  * levels N, N/2, ... while the element count stays even and the next level has
-    at least `coarse_n` elements per side; the coarse problem is rediscretised
-    with the per-element diffusivity averaged over the 4 children;
+  * levels N, N/2, ... halving while the element count is even and larger than
+    `coarse_n`; the coarse problem is rediscretised with the per-element
+    diffusivity averaged over the 4 children;
   * prolongation P = bilinear interpolation, restriction = P^T;
   * smoother: Chebyshev iteration of a given degree preconditioned by point
     Jacobi (for Q1 the vertex-patch additive Schwarz smoother of Section 3.2
@@ -67,10 +67,10 @@ def start_vector(n: int, level: int) -> np.ndarray:
     return 2.0 * ((z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)) - 1.0
 
 
-def level_sizes(N: int, coarse_n: int = 8):
+def level_sizes(N: int, coarse_n: int = 32):
     """Element counts per side of the multigrid levels, finest first."""
     sizes = [N]
-    while sizes[-1] % 2 == 0 and sizes[-1] // 2 >= coarse_n:
+    while sizes[-1] % 2 == 0 and sizes[-1] > coarse_n:
         sizes.append(sizes[-1] // 2)
     return sizes
 
@@ -154,7 +154,7 @@ class Hierarchy:
     power_its.
     """
 
-    def __init__(self, N, kappa, dt, coarse_n=8, cheb_degree=2, cheb_lo=0.25, cheb_hi=1.1, power_its=15):
+    def __init__(self, N, kappa, dt, coarse_n=32, cheb_degree=2, cheb_lo=0.25, cheb_hi=1.1, power_its=15):
         self.N = N
         self.dt = dt
         self.sizes = level_sizes(N, coarse_n)

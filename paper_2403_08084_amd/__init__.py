@@ -52,6 +52,7 @@ class Options(ctypes.Structure):
         ("mg_precision", ctypes.c_int),
         ("orth", ctypes.c_int),
         ("initial_guess", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
     ]
 
 

@@ -78,8 +78,8 @@ void launch_stage_rhs(const double* u, const double* F, double* f, const double*
 // y = M x or y = K x
 void launch_mass(const double* x, double* y, Geom g, hipStream_t st);
 void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st);
-// t = vscale * v - dt * K * sum_{j<i} coef[j] z_j  (z_j planes at z + j*plane)
-void launch_gs_couple(const double* v, double vscale, const double* z, int i, const Coefs& row, double dt,
+// t = vscale * v - dt * K * sum_{j<i} coef[j] z_j  (z_j planes at z + j*plane; vscale: device scalar or null = 1)
+void launch_gs_couple(const double* v, const double* vscale, const double* z, int i, const Coefs& row, double dt,
                       const double* kappa, double* t, Geom g, hipStream_t st);
 // u += dt * sum_i b_i k_i
 void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st);
@@ -99,14 +99,14 @@ void launch_scale(double* x, long n, const double* inv_norm2_src, hipStream_t st
 // ---------------------------------------------------------------- multigrid (k_mg.hip)
 // prec: 0 = FP64 storage/compute, 1 = FP32, 2 = BF16 storage / FP32 compute.
 // DOWN: pre-smooth from zero on the fine level, write x, restrict the residual into tc (coarse).
-// t_is_f64: t is the FP64 Krylov vector (scaled by tscale) instead of level storage.
-void launch_mg_down(int prec, bool t_is_f64, const void* t, double tscale, void* x, void* tc, const void* kappa,
+// t_is_f64: t is the FP64 Krylov vector (scaled by the device scalar *tscale; null = 1) instead of level storage.
+void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, const void* kappa,
                     Geom g, Geom gc, const MGCoef& c, hipStream_t st);
 // UP: x0 = x + P e, post-smooth, write out (FP64 if out_is_f64).
-void launch_mg_up(int prec, bool io_is_f64, const void* t, double tscale, const void* x, const void* e, void* out,
+void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
                   const void* kappa, Geom g, Geom gc, const MGCoef& c, hipStream_t st);
 // coarsest level: out = Binv * t on the interior nodes
-void launch_mg_coarse(int prec, bool io_is_f64, const void* t, double tscale, void* out, const void* Binv, Geom g,
+void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
                       hipStream_t st);
 
 // ---------------------------------------------------------------- Krylov (k_krylov.hip)

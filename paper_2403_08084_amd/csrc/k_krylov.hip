@@ -6,11 +6,15 @@
 //   always      |w|^2
 // so a classical Gram-Schmidt step with re-orthogonalisation costs two or three
 // streaming passes over the basis, each fusing the axpy of one projection with
-// the dot products of the next. Reductions are deterministic: every block
-// reduces its share in a fixed order (wavefront shuffles, then LDS), writes one
-// partial row, and the last block to finish (device-scope counter) sums the
-// partial rows in block order and writes the results, the optional inverse norm
-// and the optional re-orthogonalisation flag. No floating-point atomics.
+// the dot products of the next. The vector count is a compile-time parameter
+// (one instantiation per count and mode) so every loop unrolls without
+// guards and each thread keeps all of its loads in flight.
+//
+// Reductions are deterministic: every block reduces its share in a fixed order
+// (wavefront shuffles, then LDS) and writes one partial per value; a one-block
+// finishing kernel sums the partials with all its threads in a fixed strided
+// order followed by the same tree, and writes the results, the optional inverse
+// norm and the optional re-orthogonalisation flag. No atomics, no fences.
 #include "irk_internal.h"
 
 namespace irk {
@@ -18,7 +22,8 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NW = NT / 64;
-constexpr int kStride = kMaxRestart + 1;
+
+enum Mode { NORM = 0, DOTS = 1, AXPY_DOTS = 2, AXPY = 3 };
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -26,111 +31,173 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int MAXV>
-__global__ __launch_bounds__(NT) void ortho_kernel(OrthoArgs a, ReduceWork rw) {
-  if (a.skip && *a.skip == 0) return;
-  const int nv = a.nv;
-  const bool do_axpy = a.coef != nullptr;
-  const bool do_dots = a.want_dots != 0;
-  double c[MAXV];
-#pragma unroll
-  for (int k = 0; k < MAXV; ++k) {
-    double v = 0.0;
-    if (do_axpy && k < nv) v = a.coef_sign * a.coef[k] * (a.vscale ? a.vscale[k] : 1.0);
-    c[k] = v;
-  }
-  double d[MAXV];
-#pragma unroll
-  for (int k = 0; k < MAXV; ++k) d[k] = 0.0;
-  double nrm = 0.0;
-  const long stride = (long)gridDim.x * NT;
-  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < a.len; q += stride) {
-    double wv = a.w[q];
-    if (do_axpy) {
-      double v[MAXV];
-#pragma unroll
-      for (int k = 0; k < MAXV; ++k)
-        if (k < nv) v[k] = a.V[k * a.vstride + q];
-#pragma unroll
-      for (int k = 0; k < MAXV; ++k)
-        if (k < nv) wv -= c[k] * v[k];
-      a.w[q] = wv;
-      if (do_dots) {
-#pragma unroll
-        for (int k = 0; k < MAXV; ++k)
-          if (k < nv) d[k] += v[k] * wv;
-      }
-    } else if (do_dots) {
-#pragma unroll
-      for (int k = 0; k < MAXV; ++k)
-        if (k < nv) d[k] += a.V[k * a.vstride + q] * wv;
-    }
-    nrm += wv * wv;
-  }
-  // block reduction: wavefront shuffle, then across the NW wavefronts
-  __shared__ double red[(MAXV + 1) * NW];
+// Reduce vals[0..CNT) over the block into out_smem[0..CNT) (fixed order).
+template <int CNT>
+__device__ __forceinline__ void block_reduce(const double (&vals)[CNT], double* red, double* out_smem) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < MAXV; ++k) {
-    if (k < nv && do_dots) {
-      const double s = wave_sum(d[k]);
-      if (lane == 0) red[k * NW + wid] = s;
-    }
-  }
-  {
-    const double s = wave_sum(nrm);
-    if (lane == 0) red[MAXV * NW + wid] = s;
+  for (int k = 0; k < CNT; ++k) {
+    const double s = wave_sum(vals[k]);
+    if (lane == 0) red[k * NW + wid] = s;
   }
   __syncthreads();
-  double* part = rw.partial + (long)blockIdx.x * kStride;
-  for (int k = threadIdx.x; k <= nv; k += NT) {
-    const int slot = (k == nv) ? MAXV : k;
-    if (k < nv && !do_dots) {
-      part[k] = 0.0;
-      continue;
-    }
+  for (int k = threadIdx.x; k < CNT; k += NT) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) s += red[slot * NW + w];
-    part[k] = s;
+    for (int w = 0; w < NW; ++w) s += red[k * NW + w];
+    out_smem[k] = s;
   }
-  __threadfence();
-  __shared__ int is_last;
-  if (threadIdx.x == 0) is_last = (atomicAdd(rw.counter, 1u) == gridDim.x - 1);
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  for (int k = threadIdx.x; k <= nv; k += NT) {
+}
+
+template <int NV, int MODE, int U>
+__device__ __forceinline__ void process(const OrthoArgs& a, const double (&c)[NV > 0 ? NV : 1], long q0, long stride,
+                                        double (&acc)[NV + 1]) {
+  constexpr bool AX = (MODE == AXPY_DOTS || MODE == AXPY);
+  constexpr bool DT = (MODE == AXPY_DOTS || MODE == DOTS);
+  constexpr bool NEEDV = AX || DT;
+  constexpr int NVV = NV > 0 ? NV : 1;
+  double wv[U];
+  double v[U][NVV];
+#pragma unroll
+  for (int u = 0; u < U; ++u) wv[u] = a.w[q0 + u * stride];
+  if (NEEDV) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = a.V[k * a.vstride + q0 + u * stride];
+  }
+  if (AX) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) wv[u] -= c[k] * v[u][k];
+      a.w[q0 + u * stride] = wv[u];
+    }
+  }
+  if (DT) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += v[u][k] * wv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[NV] += wv[u] * wv[u];
+}
+
+template <int NV, int MODE>
+__global__ __launch_bounds__(NT) void ortho_kernel(OrthoArgs a, ReduceWork rw) {
+  if (a.skip && *a.skip == 0) return;
+  constexpr bool AX = (MODE == AXPY_DOTS || MODE == AXPY);
+  constexpr int NVV = NV > 0 ? NV : 1;
+  constexpr int U = NV <= 2 ? 4 : (NV <= 8 ? 2 : 1);
+  double c[NVV];
+#pragma unroll
+  for (int k = 0; k < NVV; ++k) c[k] = (AX && k < NV) ? a.coef_sign * a.coef[k] * (a.vscale ? a.vscale[k] : 1.0) : 0.0;
+  double acc[NV + 1];
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) acc[k] = 0.0;
+  const long stride = (long)gridDim.x * NT;
+  const long len = a.len;
+  long q0 = (long)blockIdx.x * NT + threadIdx.x;
+  for (; q0 + (U - 1) * stride < len; q0 += U * stride) process<NV, MODE, U>(a, c, q0, stride, acc);
+  for (; q0 < len; q0 += stride) process<NV, MODE, 1>(a, c, q0, stride, acc);
+
+  __shared__ double red[(NV + 1) * NW];
+  __shared__ double tot[NV + 1];
+  block_reduce<NV + 1>(acc, red, tot);
+  const int mb = rw.max_blocks;
+  for (int k = threadIdx.x; k <= NV; k += NT) rw.partial[(long)k * mb + blockIdx.x] = tot[k];
+}
+
+// Second stage (one block of NF threads, nb <= NF): thread b loads partial b of every value,
+// then a fixed-order tree. The kernel boundary makes the partials visible, so no device-scope
+// fence (which would write back and invalidate the L2 of every block's XCD) is needed.
+constexpr int NF = 1024;
+constexpr int NFW = NF / 64;
+
+template <int NV>
+__global__ __launch_bounds__(NF) void finish_kernel(OrthoArgs a, ReduceWork rw, int nb) {
+  if (a.skip && *a.skip == 0) return;
+  const int mb = rw.max_blocks;
+  const int b = threadIdx.x;
+  double fin[NV + 1];
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) fin[k] = rw.partial[(long)k * mb + (b < nb ? b : 0)];
+#pragma unroll
+  for (int k = 0; k <= NV; ++k)
+    if (b >= nb) fin[k] = 0.0;
+  __shared__ double red[(NV + 1) * NFW];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) {
+    const double s = wave_sum(fin[k]);
+    if (lane == 0) red[k * NFW + wid] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k <= NV; k += NF) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += rw.partial[(long)b * kStride + k];
-    if (k < nv) {
+#pragma unroll
+    for (int w = 0; w < NFW; ++w) s += red[k * NFW + w];
+    if (k < NV) {
       a.result[k] = s * (a.vscale ? a.vscale[k] : 1.0);
     } else {
-      a.result[nv] = s;
+      a.result[NV] = s;
       if (a.sigma_out) *a.sigma_out = 1.0 / sqrt(s);
       if (a.flag_out) *a.flag_out = (s < a.eta2 * (*a.ref)) ? 1 : 0;
     }
   }
-  if (threadIdx.x == 0) *rw.counter = 0u;
 }
+
+using KernelFn = void (*)(OrthoArgs, ReduceWork);
+using FinishFn = void (*)(OrthoArgs, ReduceWork, int);
+
+template <int NV>
+KernelFn pick(int mode) {
+  switch (mode) {
+    case DOTS: return ortho_kernel<NV, DOTS>;
+    case AXPY_DOTS: return ortho_kernel<NV, AXPY_DOTS>;
+    default: return ortho_kernel<NV, AXPY>;
+  }
+}
+
+template <int... I>
+struct Table {
+  static KernelFn get(int nv, int mode) {
+    KernelFn out = nullptr;
+    ((nv == I + 1 ? (out = pick<I + 1>(mode), 0) : 0), ...);
+    return out;
+  }
+  static FinishFn fin(int nv) {
+    FinishFn out = nullptr;
+    ((nv == I + 1 ? (out = finish_kernel<I + 1>, 0) : 0), ...);
+    return out;
+  }
+};
+
+template <int... I>
+Table<I...> make_table(std::integer_sequence<int, I...>);
 
 }  // namespace
 
 void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st) {
   long blocks = (a.len + NT - 1) / NT;
   if (blocks > rw.max_blocks) blocks = rw.max_blocks;
+  if (blocks > NF) blocks = NF;
   if (blocks < 1) blocks = 1;
   const int nb = (int)blocks;
-  if (a.nv <= 0) {
-    ortho_kernel<1><<<nb, NT, 0, st>>>(a, rw);
-  } else if (a.nv <= 8) {
-    ortho_kernel<8><<<nb, NT, 0, st>>>(a, rw);
-  } else if (a.nv <= 16) {
-    ortho_kernel<16><<<nb, NT, 0, st>>>(a, rw);
-  } else {
-    ortho_kernel<32><<<nb, NT, 0, st>>>(a, rw);
+  const bool ax = a.coef != nullptr, dt = a.want_dots != 0;
+  if (a.nv <= 0 || (!ax && !dt)) {
+    OrthoArgs b = a;
+    b.nv = 0;
+    ortho_kernel<0, NORM><<<nb, NT, 0, st>>>(b, rw);
+    finish_kernel<0><<<1, NF, 0, st>>>(b, rw, nb);
+    return;
   }
+  const int mode = (ax && dt) ? AXPY_DOTS : (ax ? AXPY : DOTS);
+  using T = decltype(make_table(std::make_integer_sequence<int, 32>{}));
+  hipLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, a, rw);
+  hipLaunchKernelGGL(T::fin(a.nv), dim3(1), dim3(NF), 0, st, a, rw, nb);
 }
 
 }  // namespace irk

@@ -72,19 +72,31 @@ __device__ __forceinline__ TC diag_at(const TC* K, int li, int lj, TC m, TC alph
 
 __device__ __forceinline__ bool interior(int i, int j, int N) { return i >= 1 && i <= N - 1 && j >= 1 && j <= N - 1; }
 
+// Tile loads are staged through registers with fully unrolled loops, so every
+// thread has all of its global loads in flight before the first LDS store.
 template <typename TC, typename TK, int KX, int KY>
 __device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ kap, int ox, int oy, const Geom& g) {
-  for (int idx = threadIdx.x; idx < KX * KY; idx += NT) {
+  constexpr int CNT = KX * KY, NL = (CNT + NT - 1) / NT;
+  TC v[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
     const int b = idx / KX, a = idx - b * KX;
     const int ex = ox - 1 + a, ey = oy - 1 + b;
-    TC v = (TC)0;
-    if (ex >= 0 && ex < g.N && ey >= 0 && ey < g.N) v = (TC)kap[(long)ey * g.pitch + ex];
-    sK[idx] = v;
+    const bool ok = idx < CNT && ex >= 0 && ex < g.N && ey >= 0 && ey < g.N;
+    // unconditional load from a clamped address keeps all loads in flight; the select zeroes the rest
+    const TC val = (TC)kap[ok ? (long)ey * g.pitch + ex : 0];
+    v[r] = ok ? val : (TC)0;
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx < CNT) sK[idx] = v[r];
   }
 }
 
 template <typename TV, typename TS, typename TC, int DEG, int TX, int TY>
-__global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, double tscale, TS* __restrict__ xout,
+__global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, const double* __restrict__ tscale, TS* __restrict__ xout,
                                                      TS* __restrict__ tc, const TC* __restrict__ kap, Geom g, Geom gc,
                                                      MGCoef cf) {
   constexpr int H = DEG + 1;
@@ -97,16 +109,29 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, d
   const int N = g.N;
   const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
   const int ox = i0 - H, oy = j0 - H;
-  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)tscale;
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = tscale ? (TC)(*tscale) : (TC)1;
 
-  load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
-  for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
-    const int lj = idx / RX, li = idx - lj * RX;
-    const int i = ox + li, j = oy + lj;
-    TC v = (TC)0;
-    if (interior(i, j, N)) v = ld<TC>(t + (long)j * g.pitch + i) * ts;
-    sT[idx] = v;
-    sA[idx] = (TC)0;
+  {
+    constexpr int CNT = RX * RY, NL = (CNT + NT - 1) / NT;
+    TC tv[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      const int lj = idx / RX, li = idx - lj * RX;
+      const int i = ox + li, j = oy + lj;
+      const bool ok = idx < CNT && interior(i, j, N);
+      const TC val = ld<TC>(t + (ok ? (long)j * g.pitch + i : 0));
+      tv[r] = ok ? val * ts : (TC)0;
+    }
+    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      if (idx < CNT) {
+        sT[idx] = tv[r];
+        sA[idx] = (TC)0;
+      }
+    }
   }
   __syncthreads();
   // first Chebyshev step from x0 = 0 is pointwise: x1 = c0 D^{-1} t
@@ -177,19 +202,18 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, d
   }
 }
 
+// bilinear interpolation of the coarse correction at fine interior node (i, j):
+// weights 1, 1/2, 1/4 by parity; all four coarse values are loaded (always in bounds)
 template <typename TS, typename TC>
 __device__ __forceinline__ TC prolong_at(const TS* __restrict__ e, int pc, int i, int j) {
-  const int I = i >> 1, J = j >> 1;
-  const TS* b = e + (long)J * pc + I;
-  const TC e00 = ld<TC>(b);
-  if (!(i & 1) && !(j & 1)) return e00;
-  if ((i & 1) && !(j & 1)) return (TC)0.5 * (e00 + ld<TC>(b + 1));
-  if (!(i & 1) && (j & 1)) return (TC)0.5 * (e00 + ld<TC>(b + pc));
-  return (TC)0.25 * (e00 + ld<TC>(b + 1) + ld<TC>(b + pc) + ld<TC>(b + pc + 1));
+  const TS* b = e + (long)(j >> 1) * pc + (i >> 1);
+  const TC e00 = ld<TC>(b), e10 = ld<TC>(b + 1), e01 = ld<TC>(b + pc), e11 = ld<TC>(b + pc + 1);
+  const TC wx = (i & 1) ? (TC)0.5 : (TC)0, wy = (j & 1) ? (TC)0.5 : (TC)0;
+  return ((TC)1 - wx) * ((TC)1 - wy) * e00 + wx * ((TC)1 - wy) * e10 + ((TC)1 - wx) * wy * e01 + wx * wy * e11;
 }
 
 template <typename TV, typename TS, typename TC, int DEG, int TX, int TY>
-__global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, double tscale, const TS* __restrict__ x,
+__global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, const double* __restrict__ tscale, const TS* __restrict__ x,
                                                    const TS* __restrict__ e, TV* __restrict__ out,
                                                    const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf) {
   constexpr int H = DEG;
@@ -202,21 +226,34 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, dou
   const int N = g.N;
   const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
   const int ox = i0 - H, oy = j0 - H;
-  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)tscale;
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = tscale ? (TC)(*tscale) : (TC)1;
 
-  load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
-  for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
-    const int lj = idx / RX, li = idx - lj * RX;
-    const int i = ox + li, j = oy + lj;
-    TC tv = (TC)0, xv = (TC)0;
-    if (interior(i, j, N)) {
-      const long p = (long)j * g.pitch + i;
-      tv = ld<TC>(t + p) * ts;
-      xv = ld<TC>(x + p) + prolong_at<TS, TC>(e, gc.pitch, i, j);
+  {
+    constexpr int CNT = RX * RY, NL = (CNT + NT - 1) / NT;
+    TC tv[NL], xv[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      const int lj = idx / RX, li = idx - lj * RX;
+      const int i = ox + li, j = oy + lj;
+      const bool ok = idx < CNT && interior(i, j, N);
+      const int ic = ok ? i : 1, jc = ok ? j : 1;
+      const long p = (long)jc * g.pitch + ic;
+      const TC a = ld<TC>(t + p) * ts;
+      const TC b = ld<TC>(x + p) + prolong_at<TS, TC>(e, gc.pitch, ic, jc);
+      tv[r] = ok ? a : (TC)0;
+      xv[r] = ok ? b : (TC)0;
     }
-    sT[idx] = tv;
-    sA[idx] = xv;
-    sB[idx] = (TC)0;
+    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      if (idx < CNT) {
+        sT[idx] = tv[r];
+        sA[idx] = xv[r];
+        sB[idx] = (TC)0;
+      }
+    }
   }
   __syncthreads();
   // first step from the corrected x0: x1 = x0 + c0 D^{-1} (t - B x0)
@@ -259,22 +296,31 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, dou
   }
 }
 
+// Coarsest level: out = Binv * t on the n = (N-1)^2 interior nodes. One wavefront per
+// row (lanes stride the row, coalesced), the compacted right-hand side staged in LDS by
+// every block, a fixed-order wavefront reduction per row.
 template <typename TI, typename TO, typename TC>
-__global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t, double tscale, TO* __restrict__ out,
-                                                       const TC* __restrict__ Binv, Geom g) {
+__global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t, const double* __restrict__ tscale,
+                                                       TO* __restrict__ out, const TC* __restrict__ Binv, Geom g) {
   __shared__ TC sv[kMaxCoarse];
   const int m = g.N - 1;
   const int n = m * m;
+  const TC tsc = tscale ? (TC)(*tscale) : (TC)1;
   for (int q = threadIdx.x; q < n; q += NT) {
     const int j = q / m + 1, i = q % m + 1;
-    sv[q] = ld<TC>(t + (long)j * g.pitch + i) * (TC)tscale;
+    sv[q] = ld<TC>(t + (long)j * g.pitch + i) * tsc;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < n; q += NT) {
-    const TC* row = Binv + (long)q * n;
-    TC acc = (TC)0;
-    for (int r = 0; r < n; ++r) acc += row[r] * sv[r];
-    const int j = q / m + 1, i = q % m + 1;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const TC* r = Binv + (long)row * n;
+  TC acc = (TC)0;
+  for (int c = lane; c < n; c += 64) acc += r[c] * sv[c];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    const int j = row / m + 1, i = row % m + 1;
     st(out + (long)j * g.pitch + i, acc);
   }
 }
@@ -282,7 +328,7 @@ __global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t,
 constexpr int TXD = 64, TYD = 16;
 
 template <typename TV, typename TS, typename TC>
-void down_t(const void* t, double tscale, void* x, void* tc, const void* kap, Geom g, Geom gc, const MGCoef& c,
+void down_t(const void* t, const double* tscale, void* x, void* tc, const void* kap, Geom g, Geom gc, const MGCoef& c,
             hipStream_t st) {
   const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
   const TV* tt = (const TV*)t;
@@ -297,7 +343,7 @@ void down_t(const void* t, double tscale, void* x, void* tc, const void* kap, Ge
 }
 
 template <typename TV, typename TS, typename TC>
-void up_t(const void* t, double tscale, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
+void up_t(const void* t, const double* tscale, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
           const MGCoef& c, hipStream_t st) {
   const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
   const TV* tt = (const TV*)t;
@@ -314,7 +360,7 @@ void up_t(const void* t, double tscale, const void* x, const void* e, void* out,
 
 }  // namespace
 
-void launch_mg_down(int prec, bool t_is_f64, const void* t, double tscale, void* x, void* tc, const void* kappa,
+void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, const void* kappa,
                     Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
   if (prec == 0) {
     down_t<double, double, double>(t, tscale, x, tc, kappa, g, gc, c, st);
@@ -331,7 +377,7 @@ void launch_mg_down(int prec, bool t_is_f64, const void* t, double tscale, void*
   }
 }
 
-void launch_mg_up(int prec, bool io_is_f64, const void* t, double tscale, const void* x, const void* e, void* out,
+void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
                   const void* kappa, Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
   if (prec == 0) {
     up_t<double, double, double>(t, tscale, x, e, out, kappa, g, gc, c, st);
@@ -348,20 +394,24 @@ void launch_mg_up(int prec, bool io_is_f64, const void* t, double tscale, const 
   }
 }
 
-void launch_mg_coarse(int prec, bool io_is_f64, const void* t, double tscale, void* out, const void* Binv, Geom g,
+void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
                       hipStream_t st) {
+  const int n = (g.N - 1) * (g.N - 1);
+  const dim3 grid((n + NT / 64 - 1) / (NT / 64));
   if (prec == 0) {
-    mg_coarse_kernel<double, double, double><<<1, NT, 0, st>>>((const double*)t, tscale, (double*)out,
-                                                              (const double*)Binv, g);
+    mg_coarse_kernel<double, double, double><<<grid, NT, 0, st>>>((const double*)t, tscale, (double*)out,
+                                                                 (const double*)Binv, g);
   } else if (io_is_f64) {
-    mg_coarse_kernel<double, double, float><<<1, NT, 0, st>>>((const double*)t, tscale, (double*)out,
-                                                             (const float*)Binv, g);
+    mg_coarse_kernel<double, double, float><<<grid, NT, 0, st>>>((const double*)t, tscale, (double*)out,
+                                                                (const float*)Binv, g);
   } else if (prec == 1) {
-    mg_coarse_kernel<float, float, float><<<1, NT, 0, st>>>((const float*)t, tscale, (float*)out,
-                                                           (const float*)Binv, g);
+    mg_coarse_kernel<float, float, float><<<grid, NT, 0, st>>>((const float*)t, tscale, (float*)out,
+                                                              (const float*)Binv, g);
   } else {
-    mg_coarse_kernel<bf16, bf16, float><<<1, NT, 0, st>>>((const bf16*)t, tscale, (bf16*)out, (const float*)Binv, g);
+    mg_coarse_kernel<bf16, bf16, float><<<grid, NT, 0, st>>>((const bf16*)t, tscale, (bf16*)out, (const float*)Binv,
+                                                            g);
   }
 }
 
 }  // namespace irk
+

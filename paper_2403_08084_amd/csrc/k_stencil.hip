@@ -201,7 +201,7 @@ __global__ __launch_bounds__(BX* BY) void stiff_kernel(const double* __restrict_
   y[p] = stiff(load_nb(x, p, g.pitch), load_kap(kap, p, g.pitch));
 }
 
-__global__ __launch_bounds__(BX* BY) void gs_couple_kernel(const double* __restrict__ v, double vscale,
+__global__ __launch_bounds__(BX* BY) void gs_couple_kernel(const double* __restrict__ v, const double* __restrict__ vscale,
                                                            const double* __restrict__ z, int ns, Coefs row, double dt,
                                                            const double* __restrict__ kap, double* __restrict__ t,
                                                            Geom g) {
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(BX* BY) void gs_couple_kernel(const double* __restr
   const Kap k = load_kap(kap, p, P);
   double acc = 0.0;
   for (int q = 0; q < ns; ++q) acc += row.a[q] * stiff(load_nb(z + q * g.plane, p, P), k);
-  t[p] = vscale * v[p] - dt * acc;
+  t[p] = (vscale ? *vscale : 1.0) * v[p] - dt * acc;
 }
 
 __global__ void update_kernel(double* __restrict__ u, const double* __restrict__ k, int s, Coefs b, double dt,
@@ -372,7 +372,7 @@ void launch_mass(const double* x, double* y, Geom g, hipStream_t st) {
 void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st) {
   stiff_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, y, kappa, g);
 }
-void launch_gs_couple(const double* v, double vscale, const double* z, int i, const Coefs& row, double dt,
+void launch_gs_couple(const double* v, const double* vscale, const double* z, int i, const Coefs& row, double dt,
                       const double* kappa, double* t, Geom g, hipStream_t st) {
   gs_couple_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(v, vscale, z, i, row, dt, kappa, t, g);
 }

@@ -114,6 +114,8 @@ struct irk_stepper {
   double* hres = nullptr; // pinned host mirror of dres
   ReduceWork rw{};
   bool have_prev = false;
+  hipStream_t cap = nullptr;              // library-owned stream used only to capture graphs
+  std::vector<hipGraphExec_t> graphs[2];  // one per Arnoldi index j, forward / transposed
 };
 
 namespace {
@@ -284,7 +286,7 @@ int coarse_inverse(const std::vector<double>& kap, int N, double alpha, std::vec
 int setup_multigrid(irk_stepper* st, hipStream_t s) {
   const irk_problem* p = st->prob;
   std::vector<int> sizes{p->N};
-  while (sizes.back() % 2 == 0 && sizes.back() / 2 >= st->opt.mg_coarse_n) sizes.push_back(sizes.back() / 2);
+  while (sizes.back() % 2 == 0 && sizes.back() > st->opt.mg_coarse_n) sizes.push_back(sizes.back() / 2);
   const int Nc = sizes.back();
   if ((long)(Nc - 1) * (Nc - 1) > kMaxCoarse)
     return fail(IRK_EINVAL, "multigrid needs N = Nc * 2^L with (Nc-1)^2 <= 1024; N = " + std::to_string(p->N) +
@@ -370,7 +372,7 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
 // ------------------------------------------------------------------ preconditioner
 
 // out = one V-cycle for block `stage` applied to tscale * t (FP64 padded planes)
-int vcycle(irk_stepper* st, int stage, const double* t, double tscale, double* out, hipStream_t s) {
+int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, double* out, hipStream_t s) {
   const int L = (int)st->lv.size();
   const MGCoef* cf = &st->coef[(size_t)stage * L];
   const int pr = st->prec;
@@ -381,16 +383,16 @@ int vcycle(irk_stepper* st, int stage, const double* t, double tscale, double* o
   std::vector<Level>& lv = st->lv;
   launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
   for (int l = 1; l < L - 1; ++l)
-    launch_mg_down(pr, false, lv[l].t, 1.0, lv[l].x, lv[l + 1].t, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
-  launch_mg_coarse(pr, false, lv[L - 1].t, 1.0, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
+    launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+  launch_mg_coarse(pr, false, lv[L - 1].t, nullptr, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
   for (int l = L - 2; l >= 1; --l)
-    launch_mg_up(pr, false, lv[l].t, 1.0, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+    launch_mg_up(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
   launch_mg_up(pr, true, t, tscale, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
   return check_launch();
 }
 
-// z = P^{-1} (vscale * v), block Jacobi or block lower Gauss-Seidel in the AI form
-int precondition(irk_stepper* st, const double* v, double vscale, double* z, bool trans, hipStream_t s) {
+// z = P^{-1} (vscale * v), block Jacobi or block lower Gauss-Seidel in the AI form (vscale: device scalar or null)
+int precondition(irk_stepper* st, const double* v, const double* vscale, double* z, bool trans, hipStream_t s) {
   const long plane = st->g.plane;
   const Coefs a = coefs_of(st, trans);
   for (int i = 0; i < st->s; ++i) {
@@ -401,7 +403,7 @@ int precondition(irk_stepper* st, const double* v, double vscale, double* z, boo
       for (int j = 0; j < i; ++j) row.a[j] = a.a[i * kMaxStages + j];
       double* t = st->tmp2;
       launch_gs_couple(vi, vscale, z, i, row, st->dt, st->prob->kappa, t, st->g, s);
-      CHK(vcycle(st, i, t, 1.0, zi, s));
+      CHK(vcycle(st, i, t, nullptr, zi, s));
     } else {
       CHK(vcycle(st, i, vi, vscale, zi, s));
     }
@@ -412,6 +414,76 @@ int precondition(irk_stepper* st, const double* v, double vscale, double* z, boo
 int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s) {
   launch_stage_operator(x, y, f, st->prob->kappa, st->g, st->s, coefs_of(st, trans), st->dt, s);
   return check_launch();
+}
+
+// ------------------------------------------------------------------ Arnoldi step
+
+// Everything one FGMRES iteration j enqueues between two host decisions:
+// Z_j = P^{-1}(sigma_j V_j), w = Acal Z_j into V_{j+1}, then classical Gram-Schmidt
+// with re-orthogonalisation (passes A, B, C) against V_0..V_j. Scales are read
+// from device memory, so the sequence is replayable as a graph.
+int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
+  const long n = st->vlen;
+  double* sig = sigma_dev(st);
+  double* Vj = st->V + (long)j * n;
+  double* Vn = st->V + (long)(j + 1) * n;
+  double* Zj = st->Z + (long)j * n;
+  CHK(precondition(st, Vj, sig + j, Zj, trans, s));
+  CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
+  // pass A: h = V^T w, |w|^2
+  OrthoArgs a = ortho_base();
+  a.V = st->V;
+  a.vstride = n;
+  a.nv = j + 1;
+  a.w = Vn;
+  a.len = n;
+  a.vscale = sig;
+  a.want_dots = 1;
+  a.result = res_slot(st, 0);
+  CHK(ortho(st, a, s));
+  // pass B: w -= V h; h2 = V^T w; |w|^2; flag = |w|^2 < eta^2 |w_before|^2
+  OrthoArgs b = a;
+  b.coef = res_slot(st, 0);
+  b.result = res_slot(st, 1);
+  b.sigma_out = sig + (j + 1);
+  b.flag_out = st->dflag;
+  b.ref = res_slot(st, 0) + (j + 1);
+  b.eta2 = 0.5;
+  CHK(ortho(st, b, s));
+  // pass C: w -= V h2; |w|^2 (skipped unless needed for the selective variant)
+  OrthoArgs c = a;
+  c.coef = res_slot(st, 1);
+  c.want_dots = 0;
+  c.result = res_slot(st, 2);
+  c.sigma_out = sig + (j + 1);
+  c.skip = st->opt.orth == IRK_ORTH_CGS_SELECTIVE ? st->dflag : nullptr;
+  CHK(ortho(st, c, s));
+  return IRK_OK;
+}
+
+// Enqueue Arnoldi step j on s: replay its captured graph (captured on first use), or eagerly.
+int run_arnoldi(irk_stepper* st, int j, bool trans, hipStream_t s) {
+  if (!st->opt.use_graphs) return arnoldi_body(st, j, trans, s);
+  std::vector<hipGraphExec_t>& gs = st->graphs[trans ? 1 : 0];
+  if (gs.empty()) gs.assign(st->opt.restart, nullptr);
+  if (!gs[j]) {
+    HIPCHK(hipStreamBeginCapture(st->cap, hipStreamCaptureModeRelaxed));
+    const int rc = arnoldi_body(st, j, trans, st->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st->cap, &graph);
+    if (rc != IRK_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(IRK_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return fail(IRK_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    gs[j] = ge;
+  }
+  HIPCHK(hipGraphLaunch(gs[j], s));
+  return IRK_OK;
 }
 
 // ------------------------------------------------------------------ FGMRES
@@ -464,39 +536,7 @@ int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveIn
     int jdone = 0;
     bool converged_est = false;
     for (int j = 0; j < m; ++j) {
-      double* Vj = st->V + (long)j * n;
-      double* Vn = st->V + (long)(j + 1) * n;
-      double* Zj = st->Z + (long)j * n;
-      CHK(precondition(st, Vj, sig_h[j], Zj, trans, s));
-      CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
-      // pass A: h = V^T w, |w|^2
-      OrthoArgs a = ortho_base();
-      a.V = st->V;
-      a.vstride = n;
-      a.nv = j + 1;
-      a.w = Vn;
-      a.len = n;
-      a.vscale = sig;
-      a.want_dots = 1;
-      a.result = res_slot(st, 0);
-      CHK(ortho(st, a, s));
-      // pass B: w -= V h; h2 = V^T w; |w|^2; flag = |w|^2 < eta^2 |w_before|^2
-      OrthoArgs b = a;
-      b.coef = res_slot(st, 0);
-      b.result = res_slot(st, 1);
-      b.sigma_out = sig + (j + 1);
-      b.flag_out = st->dflag;
-      b.ref = res_slot(st, 0) + (j + 1);
-      b.eta2 = 0.5;
-      CHK(ortho(st, b, s));
-      // pass C: w -= V h2; |w|^2 (skipped unless needed for the selective variant)
-      OrthoArgs c = a;
-      c.coef = res_slot(st, 1);
-      c.want_dots = 0;
-      c.result = res_slot(st, 2);
-      c.sigma_out = sig + (j + 1);
-      c.skip = selective ? st->dflag : nullptr;
-      CHK(ortho(st, c, s));
+      CHK(run_arnoldi(st, j, trans, s));
       HIPCHK(hipMemcpyAsync(h, st->dres, 3L * RSTRIDE * sizeof(double), hipMemcpyDeviceToHost, s));
       int flag = 1;
       if (selective) HIPCHK(hipMemcpyAsync(&flag, st->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -695,7 +735,7 @@ void irk_options_default(irk_options* o) {
   o->rtol = 1e-10;
   o->restart = 30;
   o->max_it = 300;
-  o->mg_coarse_n = 8;
+  o->mg_coarse_n = 32;
   o->cheb_degree = 2;
   o->cheb_lo = 0.25;
   o->cheb_hi = 1.1;
@@ -703,6 +743,7 @@ void irk_options_default(irk_options* o) {
   o->mg_precision = IRK_F64;
   o->orth = IRK_ORTH_CGS2;
   o->initial_guess = IRK_GUESS_ZERO;
+  o->use_graphs = 1;
 }
 
 int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stream) {
@@ -813,6 +854,10 @@ void irk_stepper_destroy(irk_stepper* st) {
   dev_free(st->dflag);
   dev_free(st->rw.partial);
   dev_free(st->rw.counter);
+  for (auto& v : st->graphs)
+    for (hipGraphExec_t g : v)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (st->cap) (void)hipStreamDestroy(st->cap);
   if (st->hres) (void)hipHostFree(st->hres);
   delete st;
 }
@@ -839,7 +884,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   if (o.orth != IRK_ORTH_CGS2 && o.orth != IRK_ORTH_CGS_SELECTIVE) return fail(IRK_EINVAL, "unknown orth");
   if (o.initial_guess != IRK_GUESS_ZERO && o.initial_guess != IRK_GUESS_PREV)
     return fail(IRK_EINVAL, "unknown initial_guess");
-  if (o.mg_coarse_n < 2) return fail(IRK_EINVAL, "mg_coarse_n must be >= 2");
+  if (o.mg_coarse_n < 1) return fail(IRK_EINVAL, "mg_coarse_n must be >= 1");
   const int s = tab->s;
   for (int i = 0; i < s * s; ++i)
     if (!std::isfinite(tab->A[i])) return fail(IRK_EINVAL, "non-finite tableau entry");
@@ -892,6 +937,8 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   }
   if (rc == IRK_OK && hipHostMalloc((void**)&st->hres, DRES_LEN * sizeof(double)) != hipSuccess)
     rc = fail(IRK_ENOMEM, "hipHostMalloc failed");
+  if (rc == IRK_OK && hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(IRK_EHIP, "stream creation failed");
   if (rc == IRK_OK) rc = setup_multigrid(st, hs);
   if (rc == IRK_OK && hipStreamSynchronize(hs) != hipSuccess) rc = fail(IRK_EHIP, "setup synchronisation failed");
   if (rc != IRK_OK) {
@@ -952,7 +999,7 @@ int irk_apply_preconditioner(const irk_stepper* cst, const double* v, double* z,
   irk_stepper* st = const_cast<irk_stepper*>(cst);
   hipStream_t s = S(stream);
   launch_pack(v, st->f, st->g, st->s, s);
-  CHK(precondition(st, st->f, 1.0, st->k, transpose != 0, s));
+  CHK(precondition(st, st->f, nullptr, st->k, transpose != 0, s));
   launch_unpack(st->k, z, st->g, st->s, s);
   return check_launch();
 }
@@ -965,7 +1012,7 @@ int irk_vcycle(const irk_stepper* cst, int stage, const double* t, double* z, vo
   irk_stepper* st = const_cast<irk_stepper*>(cst);
   hipStream_t s = S(stream);
   launch_pack(t, st->f, st->g, 1, s);
-  CHK(vcycle(st, stage, st->f, 1.0, st->k, s));
+  CHK(vcycle(st, stage, st->f, nullptr, st->k, s));
   launch_unpack(st->k, z, st->g, 1, s);
   return check_launch();
 }

@@ -11,13 +11,14 @@ from gpu_util import dev, host, make, rel
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("N,dt,deg", [(64, 1e-3, 2), (96, 1e-3, 2), (128, 5e-4, 2), (32, 1.0 / 32, 2), (64, 1e-3, 1),
-                                      (64, 1e-3, 3), (8, 1e-3, 2)])
-def test_vcycle_fp64_matches_oracle(N, dt, deg):
+@pytest.mark.parametrize("N,dt,deg,cn", [(64, 1e-3, 2, 8), (96, 1e-3, 2, 8), (128, 5e-4, 2, 8), (32, 1.0 / 32, 2, 8),
+                                         (64, 1e-3, 1, 8), (64, 1e-3, 3, 8), (8, 1e-3, 2, 8), (256, 1e-3, 2, 32),
+                                         (96, 1e-3, 2, 32), (66, 1e-3, 2, 32)])
+def test_vcycle_fp64_matches_oracle(N, dt, deg, cn):
     kap = synth.grf_kappa(N, 1)
     otab = OT.radau_iia(3)
-    hier = mg.Hierarchy(N, kap, dt, cheb_degree=deg)
-    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, cheb_degree=deg)
+    hier = mg.Hierarchy(N, kap, dt, cheb_degree=deg, coarse_n=cn)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, cheb_degree=deg, mg_coarse_n=cn)
     assert stp.levels == len(hier.sizes)
     t = np.random.default_rng(7).standard_normal((N - 1) ** 2)
     for i in range(3):

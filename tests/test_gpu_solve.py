@@ -175,3 +175,21 @@ def test_invalid_tableau_rejected():
     with pytest.raises(P.IrkError) as e:
         P.Stepper(prob, explicit, 1e-3)
     assert e.value.code == P.IRK_EINVAL
+
+
+@pytest.mark.parametrize("prec", [P.F64, P.F32])
+def test_graph_replay_matches_eager_bitwise(prec):
+    # every Arnoldi step is replayed from a captured graph; eager launches must give identical bits
+    N, dt, nsteps = 64, 1e-3, 3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    outs = []
+    for g in (0, 1):
+        _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, use_graphs=g, mg_precision=prec, restart=6)
+        u = dev(u0)
+        stp.advance(u, nsteps)  # restart = 6 forces restarts: graphs replay across cycles and steps
+        u2 = dev(u0)
+        stp.advance(u2, nsteps)  # second call: replays again after eager pack/unpack work
+        outs.append((host(u), host(u2)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[1][0], outs[1][1])

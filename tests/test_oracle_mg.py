@@ -20,9 +20,12 @@ def test_splitmix64_reference_value():
 
 
 def test_level_sizes():
-    assert mg.level_sizes(1024) == [1024, 512, 256, 128, 64, 32, 16, 8]
-    assert mg.level_sizes(96) == [96, 48, 24, 12]
+    assert mg.level_sizes(1024, 8) == [1024, 512, 256, 128, 64, 32, 16, 8]
+    assert mg.level_sizes(1024) == [1024, 512, 256, 128, 64, 32]
+    assert mg.level_sizes(96, 8) == [96, 48, 24, 12, 6]
+    assert mg.level_sizes(96) == [96, 48, 24]
     assert mg.level_sizes(8) == [8]
+    assert mg.level_sizes(33) == [33]
 
 
 def test_prolongation_is_bilinear_interpolation():
@@ -92,7 +95,7 @@ def test_power_mu_estimate():
 def test_single_level_vcycle_is_exact():
     N = 8
     kap = synth.grf_kappa(N, 2)
-    h = mg.Hierarchy(N, kap, 1e-3)
+    h = mg.Hierarchy(N, kap, 1e-3, coarse_n=8)
     assert h.sizes == [8]
     M, K = fem.assemble(N, kap)
     t = np.random.default_rng(0).standard_normal((N - 1) ** 2)
@@ -104,7 +107,7 @@ def test_vcycle_symmetric_and_contracting():
     N = 64
     kap = synth.grf_kappa(N, 1)
     dt, a = 1e-3, 0.2
-    hier = mg.Hierarchy(N, kap, dt)
+    hier = mg.Hierarchy(N, kap, dt, coarse_n=8)
     M, K = fem.assemble(N, kap)
     B = (M + dt * a * K).tocsr()
     rng = np.random.default_rng(3)
