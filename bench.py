@@ -10,22 +10,33 @@ preconditioner, one geometric-multigrid V-cycle (Chebyshev degree 2) per
 diagonal block. A bench "step" is one time step (stage right-hand side, the
 FGMRES stage solve with its preconditioner, the update). The timed value uses
 the mixed form (FP32 multigrid inside FP64 FGMRES); the FP64 form is measured in
-the same run and reported beside it.
+the same run and reported beside it, and both are checked against the CPU
+oracle's full-size result (tests/golden).
 
-Metric: DoF-stage-steps/s = n * s * steps / time.
+Metric: DoF-stage-steps/s = n * s * steps / time, inputs resident in HBM.
+Extra JSON objects: "roofline" (the streaming Gram-Schmidt pass, timed with HIP
+events on its launch stream by the library's measurement hook, algorithmic
+bytes vs the 8 TB/s HBM3E peak) and "cpu_baseline" (the CPU oracle on a bounded
+sample of the same workload).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "DoF-stage-steps/s at 1e-8 rel. error, RadauIIA s=3, 1024² Q1; mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "config4_radau3_1024.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "ortho_kernel_traffic.txt")
+KRYLOV_SRC = os.path.join(ROOT, "paper_2403_08084_amd", "csrc", "k_krylov.hip")
 
 
 def parse():
@@ -37,11 +48,15 @@ def parse():
     ap.add_argument("--precision", choices=["f32", "bf16", "f64"], default="f32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="time steps in the CPU oracle sample")
     ap.add_argument("--precond", choices=["gs", "jacobi"], default="gs")
     ap.add_argument("--orth", choices=["cgs2", "selective"], default="cgs2")
     ap.add_argument("--guess", choices=["zero", "prev"], default="zero")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--coarse-n", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy (counter calibration for profiles)")
     return ap.parse_args()
 
 
@@ -53,7 +68,10 @@ def solver_options(P, args):
 
 
 def timed_run(P, torch, prob, tab, dt, u0_dev, steps, warmup, prec, opts):
+    t0 = time.time()
     stp = P.Stepper(prob, tab, dt, mg_precision=prec, **opts)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
     if warmup > 0:
         uw = u0_dev.clone()
         stp.advance(uw, warmup)
@@ -65,8 +83,77 @@ def timed_run(P, torch, prob, tab, dt, u0_dev, steps, warmup, prec, opts):
     _, stats = stp.advance(u, steps)
     ev1.record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    return stp, u, ms, stats
+    return stp, u, ev0.elapsed_time(ev1), stats, setup_s
+
+
+def golden_error(u, steps):
+    """Relative L2 error of u against the oracle's full-size result (sketch estimate), or None."""
+    import numpy as np
+
+    import synth
+
+    if not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    ref = g["steps"].get(str(steps))
+    if ref is None or g["n"] != u.size:
+        return None
+    G = synth.sketch_vectors(g["n"], g["n_sketch"], g["sketch_seed"])
+    idx = np.asarray(g["indices"])
+    d = G @ u - np.asarray(ref["sketch"])
+    return {"rel_l2_sketch": float(np.sqrt(np.mean(d * d)) / ref["norm2"]),
+            "rel_max_samples": float(np.abs(u[idx] - np.asarray(ref["samples"])).max() / ref["norminf"]),
+            "rel_norm": float(abs(np.linalg.norm(u) - ref["norm2"]) / ref["norm2"])}
+
+
+def traffic_bytes_per_launch():
+    """Counter-measured HBM bytes per Gram-Schmidt pass from the committed profile summary.
+
+    Used only if the summary was taken on the current k_krylov.hip (its sha256 prefix
+    is recorded in the summary); otherwise None."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    src = hashlib.sha256(open(KRYLOV_SRC, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(TRAFFIC):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != src:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch_avg"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(N, steps):
+    """The CPU oracle (eigen-decoupled direct tier, one thread) on `steps` steps of the same workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fem, step
+    from oracle import tableaux as T
+    import synth
+
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    tab = T.radau_iia(3)
+    with threadpool_limits(1):
+        t0 = time.time()
+        M, K = fem.assemble(N, kap)
+        S = step.DecoupledLU(M, K, tab["A"], 1e-3)
+        t1 = time.time()
+        u = u0
+        for _ in range(steps):
+            k = S.solve(step.stage_rhs(K, u, 3))
+            u = step.update(u, k, tab["b"], 1e-3)
+        t2 = time.time()
+    n = (N - 1) ** 2
+    return {"value": n * 3 * steps / (t2 - t0), "unit": "DoF-stage-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{N}x{N} RadauIIA(3) workload, assembly + factorisation + {steps} time steps "
+                      f"(eigen-decoupled SuperLU, 1 thread)",
+            "setup_s": t1 - t0, "solve_s_per_step": (t2 - t1) / max(1, steps)}
 
 
 def main():
@@ -82,6 +169,12 @@ def main():
     import paper_2403_08084_amd as P
     import synth
 
+    if args.calibrate_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     N = args.N
     n = (N - 1) ** 2
     s = 3
@@ -93,8 +186,9 @@ def main():
     u0d = torch.as_tensor(u0).cuda()
     prec = {"f32": P.F32, "bf16": P.BF16, "f64": P.F64}[args.precision]
     opts = solver_options(P, args)
-    stp, u, ms, stats = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, prec, opts)
+    stp, u, ms, stats, setup_s = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, prec, opts)
     value = n * s * args.steps / (ms / 1e3)
+    uh = u.cpu().numpy()
     out = {
         "metric": METRIC,
         "value": value,
@@ -108,20 +202,40 @@ def main():
         "vs_baseline": None,
         "dtype": {"f32": "f64+f32", "bf16": "f64+bf16", "f64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"heat/diffusion Q1 {N}x{N}, GRF kappa (seed 1), RadauIIA(3), dt=1e-3, "
-                               f"FGMRES(30) rtol 1e-10, P_L + 1 GMG V-cycle Cheb(2), MG {args.precision}",
-                   "N": N, "dofs": n, "stages": s, "global_batch": 1, "seq_len": 0, "parallelism": "none"},
+        "config": {"workload": f"diffusion Q1 {N}x{N}, kappa=exp(GRF seed 1), RadauIIA(3), dt=1e-3, "
+                               f"FGMRES({args.restart}) rtol 1e-10, P_{'L' if args.precond == 'gs' else 'D'} + "
+                               f"1 GMG V-cycle Cheb(2), MG {args.precision}",
+                   "N": N, "dofs": n, "stages": s},
         "fgmres_its_per_step": stats["fgmres_its_total"] / max(1, args.steps),
+        "setup_s": setup_s,
         "solver": {"precond": args.precond, "orth": args.orth, "guess": args.guess, "restart": args.restart,
                    "coarse_n": args.coarse_n},
+        "error_vs_oracle": golden_error(uh, args.steps),
     }
     if not args.no_fp64 and prec != P.F64:
-        _, u64, ms64, st64 = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, P.F64, opts)
+        _, u64, ms64, st64, _ = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, P.F64, opts)
+        u64h = u64.cpu().numpy()
         out["fp64"] = {"value": n * s * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
-                       "fgmres_its_per_step": st64["fgmres_its_total"] / max(1, args.steps)}
+                       "fgmres_its_per_step": st64["fgmres_its_total"] / max(1, args.steps),
+                       "error_vs_oracle": golden_error(u64h, args.steps)}
         out["mixed_over_fp64"] = value / out["fp64"]["value"]
-        uh, u64h = u.cpu().numpy(), u64.cpu().numpy()
         out["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(uh - u64h) / np.linalg.norm(u64h))
+    if not args.no_roofline:
+        # same steps again with the measurement hook on the Gram-Schmidt pass (launched eagerly)
+        stp.kernel_timer(0, True)
+        u2 = u0d.clone()
+        stp.advance(u2, args.steps)
+        launches, kms, kbytes = stp.kernel_timer_read()
+        stp.kernel_timer(0, False)
+        achieved = kbytes / (kms / 1e3) / 1e9
+        tb = traffic_bytes_per_launch()
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
+                           "kernel": "ortho_kernel (streaming Gram-Schmidt pass)", "launches": launches,
+                           "avg_us": 1e3 * kms / max(1, launches),
+                           "algorithmic_bytes_per_launch": kbytes / max(1, launches)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N, args.cpu_steps)
     print(json.dumps(out))
 
 

@@ -183,6 +183,17 @@ int irk_stepper_sizes(const irk_stepper *st, int *N, int *s, int *levels);
  * multigrid level `level` (0 = finest) for stage `stage`; *mu = 0 on the coarsest level. */
 int irk_stepper_mu(const irk_stepper *st, int stage, int level, double *mu);
 
+/* Measurement hook. While enabled, every launch of kernel `family` on a full stage
+ * block is bracketed by HIP events recorded on the stream it is launched on, and its
+ * algorithmic bytes are accumulated; Krylov iterations are launched eagerly (not
+ * replayed from graphs) meanwhile, with the same kernels and arithmetic.
+ * family 0 = the streaming Gram-Schmidt pass (basis vectors read, w read, w written
+ * when updated; 8 bytes per interior value). Enabling resets the counters. */
+int irk_kernel_timer(irk_stepper *st, int family, int enable);
+/* Launches timed, their summed duration (ms) and their summed algorithmic bytes.
+ * Synchronises on the recorded events. */
+int irk_kernel_timer_read(irk_stepper *st, int *launches, double *total_ms, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

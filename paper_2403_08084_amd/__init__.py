@@ -87,7 +87,7 @@ SYMBOLS = [
     "irk_last_error", "irk_options_default", "irk_problem_create", "irk_problem_destroy", "irk_apply_mass",
     "irk_apply_stiffness", "irk_stepper_create", "irk_stepper_destroy", "irk_stage_rhs", "irk_apply_stage_operator",
     "irk_apply_preconditioner", "irk_vcycle", "irk_solve_stages", "irk_advance", "irk_adjoint",
-    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu",
+    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_kernel_timer", "irk_kernel_timer_read",
 ]
 
 
@@ -124,6 +124,8 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int)]
     L.irk_stepper_sizes.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)]
     L.irk_stepper_mu.argtypes = [vp, ip, ip, dp]
+    L.irk_kernel_timer.argtypes = [vp, ip, ip]
+    L.irk_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ip), dp, dp]
     for name in SYMBOLS:
         if name not in ("irk_last_error", "irk_options_default", "irk_problem_destroy", "irk_stepper_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -247,6 +249,18 @@ class Stepper:
         v = ctypes.c_double()
         _check(lib().irk_stepper_mu(self._h, stage, level, ctypes.byref(v)))
         return v.value
+
+    def kernel_timer(self, family: int = 0, enable: bool = True):
+        """Enable/disable the HIP-event measurement hook for a kernel family (0 = Gram-Schmidt pass)."""
+        _check(lib().irk_kernel_timer(self._h, int(family), int(bool(enable))))
+
+    def kernel_timer_read(self):
+        """(launches, total_ms, algorithmic_bytes) accumulated since the hook was enabled."""
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(lib().irk_kernel_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
 
     def stage_rhs(self, u, F=None, stream=None):
         f = _torch().empty(self.s * self.n, dtype=u.dtype, device=u.device)

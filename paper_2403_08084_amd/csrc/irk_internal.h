@@ -132,6 +132,8 @@ struct ReduceWork {
   unsigned* counter;   // one zeroed counter
   int max_blocks;
 };
-void launch_ortho(const OrthoArgs& a, const ReduceWork& w, hipStream_t st);
+// ev0/ev1 (optional): start/stop events of the streaming pass's own dispatch on st (not the finish)
+void launch_ortho(const OrthoArgs& a, const ReduceWork& w, hipStream_t st, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
 
 }  // namespace irk

@@ -15,6 +15,8 @@
 // finishing kernel sums the partials with all its threads in a fixed strided
 // order followed by the same tree, and writes the results, the optional inverse
 // norm and the optional re-orthogonalisation flag. No atomics, no fences.
+#include <hip/hip_ext.h>
+
 #include "irk_internal.h"
 
 namespace irk {
@@ -180,7 +182,7 @@ Table<I...> make_table(std::integer_sequence<int, I...>);
 
 }  // namespace
 
-void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st) {
+void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   long blocks = (a.len + NT - 1) / NT;
   if (blocks > rw.max_blocks) blocks = rw.max_blocks;
   if (blocks > NF) blocks = NF;
@@ -190,13 +192,20 @@ void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st) {
   if (a.nv <= 0 || (!ax && !dt)) {
     OrthoArgs b = a;
     b.nv = 0;
-    ortho_kernel<0, NORM><<<nb, NT, 0, st>>>(b, rw);
+    // with events, they are attached to the dispatch itself (kernel start/end timestamps)
+    if (ev0)
+      hipExtLaunchKernelGGL(ortho_kernel<0, NORM>, dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, b, rw);
+    else
+      ortho_kernel<0, NORM><<<nb, NT, 0, st>>>(b, rw);
     finish_kernel<0><<<1, NF, 0, st>>>(b, rw, nb);
     return;
   }
   const int mode = (ax && dt) ? AXPY_DOTS : (ax ? AXPY : DOTS);
   using T = decltype(make_table(std::make_integer_sequence<int, 32>{}));
-  hipLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, a, rw);
+  if (ev0)
+    hipExtLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a, rw);
+  else
+    hipLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, a, rw);
   hipLaunchKernelGGL(T::fin(a.nv), dim3(1), dim3(NF), 0, st, a, rw, nb);
 }
 

@@ -115,6 +115,12 @@ struct irk_stepper {
   ReduceWork rw{};
   bool have_prev = false;
   hipStream_t cap = nullptr;              // library-owned stream used only to capture graphs
+  // measurement hook: events around every launch of one kernel family (eager launches only)
+  int timer_family = -1;
+  std::vector<hipEvent_t> timer_ev;       // pairs (start, end)
+  size_t timer_used = 0;
+  double timer_bytes = 0;
+  int timer_launches = 0;
   std::vector<hipGraphExec_t> graphs[2];  // one per Arnoldi index j, forward / transposed
 };
 
@@ -141,8 +147,40 @@ Coefs b_of(const irk_stepper* st) {
 
 // ------------------------------------------------------------------ reductions
 
+// Next (start, end) event pair of the measurement hook, or nulls when the family is not timed.
+int timer_pair(irk_stepper* st, int family, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (st->timer_family != family) return IRK_OK;
+  if (st->timer_used + 2 > st->timer_ev.size()) {
+    for (int q = 0; q < 256; ++q) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      st->timer_ev.push_back(e);
+    }
+  }
+  *e0 = st->timer_ev[st->timer_used++];
+  *e1 = st->timer_ev[st->timer_used++];
+  st->timer_launches++;
+  return IRK_OK;
+}
+
+// Algorithmic bytes of one streaming Gram-Schmidt pass over s*n interior values:
+// the basis vectors it reads, w read, and w written when it updates w.
+double ortho_bytes(const irk_stepper* st, const OrthoArgs& a) {
+  const double vec = 8.0 * st->s * (double)(st->prob->N - 1) * (st->prob->N - 1);
+  const bool ax = a.coef != nullptr, dt = a.want_dots != 0;
+  const int nvec = (a.nv > 0 && (ax || dt)) ? a.nv : 0;
+  return vec * (nvec + 1 + (ax ? 1 : 0));
+}
+
 int ortho(irk_stepper* st, const OrthoArgs& a, hipStream_t s) {
-  launch_ortho(a, st->rw, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // only passes over full stage blocks are timed (not the setup's per-level norms)
+  if (a.len == st->vlen) {
+    CHK(timer_pair(st, 0, &e0, &e1));
+    if (e0) st->timer_bytes += ortho_bytes(st, a);
+  }
+  launch_ortho(a, st->rw, s, e0, e1);
   return check_launch();
 }
 
@@ -463,7 +501,7 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
 
 // Enqueue Arnoldi step j on s: replay its captured graph (captured on first use), or eagerly.
 int run_arnoldi(irk_stepper* st, int j, bool trans, hipStream_t s) {
-  if (!st->opt.use_graphs) return arnoldi_body(st, j, trans, s);
+  if (!st->opt.use_graphs || st->timer_family >= 0) return arnoldi_body(st, j, trans, s);
   std::vector<hipGraphExec_t>& gs = st->graphs[trans ? 1 : 0];
   if (gs.empty()) gs.assign(st->opt.restart, nullptr);
   if (!gs[j]) {
@@ -857,6 +895,7 @@ void irk_stepper_destroy(irk_stepper* st) {
   for (auto& v : st->graphs)
     for (hipGraphExec_t g : v)
       if (g) (void)hipGraphExecDestroy(g);
+  for (hipEvent_t e : st->timer_ev) (void)hipEventDestroy(e);
   if (st->cap) (void)hipStreamDestroy(st->cap);
   if (st->hres) (void)hipHostFree(st->hres);
   delete st;
@@ -1184,6 +1223,33 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
   }
   cleanup();
   return rc;
+}
+
+int irk_kernel_timer(irk_stepper* st, int family, int enable) {
+  g_err.clear();
+  CHK(validate_stepper(st));
+  if (family != 0) return fail(IRK_EINVAL, "unknown kernel family (0 = Gram-Schmidt pass)");
+  st->timer_family = enable ? family : -1;
+  st->timer_used = 0;
+  st->timer_bytes = 0;
+  st->timer_launches = 0;
+  return IRK_OK;
+}
+
+int irk_kernel_timer_read(irk_stepper* st, int* launches, double* total_ms, double* bytes) {
+  g_err.clear();
+  CHK(validate_stepper(st));
+  double ms = 0;
+  for (size_t q = 0; q + 1 < st->timer_used; q += 2) {
+    HIPCHK(hipEventSynchronize(st->timer_ev[q + 1]));
+    float f = 0;
+    HIPCHK(hipEventElapsedTime(&f, st->timer_ev[q], st->timer_ev[q + 1]));
+    ms += f;
+  }
+  if (launches) *launches = st->timer_launches;
+  if (total_ms) *total_ms = ms;
+  if (bytes) *bytes = st->timer_bytes;
+  return IRK_OK;
 }
 
 }  // extern "C"

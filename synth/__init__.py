@@ -26,6 +26,8 @@ __all__ = [
     "grf_kappa",
     "random_directions",
     "random_stage_block",
+    "sample_indices",
+    "sketch_vectors",
 ]
 
 
@@ -112,3 +114,13 @@ def random_stage_block(N: int, s: int, seed: int) -> np.ndarray:
     """Random s x (N-1)^2 block (stage-major), uniform in [-1, 1)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0, 1.0, size=(s, (N - 1) * (N - 1)))
+
+
+def sample_indices(n: int, count: int = 4096, seed: int = 12345) -> np.ndarray:
+    """Sorted seeded sample of `count` distinct indices in [0, n) (full-size parity spot checks)."""
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(count, n), replace=False))
+
+
+def sketch_vectors(n: int, count: int = 8, seed: int = 54321) -> np.ndarray:
+    """`count` seeded N(0, I) vectors of length n; projections onto them sketch a vector's error."""
+    return np.random.default_rng(seed).standard_normal((count, n))

@@ -1,0 +1,128 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times.
+
+Configs 3/4 (1024^2) are compared with the oracle's results stored by
+tests/golden/make_golden.py (norm, seeded samples, Gaussian sketch); config 2
+(512^2, kappa = 1) with the closed form at every step; config 5 (512^2 adjoint)
+with the oracle gradient and with central finite differences."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import step
+from oracle import tableaux as OT
+import paper_2403_08084_amd as P
+import synth
+from gpu_util import dev, host, make, rel
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _compare(u, ref, idx, G):
+    d = G @ u - np.asarray(ref["sketch"])
+    sketch = float(np.sqrt(np.mean(d * d)) / ref["norm2"])
+    samples = float(np.abs(u[idx] - np.asarray(ref["samples"])).max() / ref["norminf"])
+    return max(sketch, samples, abs(np.linalg.norm(u) - ref["norm2"]) / ref["norm2"])
+
+
+def _run_golden(g, tab, prec, pc, tol):
+    N = g["N"]
+    n = g["n"]
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    idx = np.asarray(g["indices"])
+    G = synth.sketch_vectors(n, g["n_sketch"], g["sketch_seed"])
+    _, stp = make(N, kap, tab, g["dt"], mg_precision=prec, precond=pc, rtol=1e-10)
+    u = dev(u0)
+    done = 0
+    errs = {}
+    for k in sorted(int(x) for x in g["steps"]):
+        stp.advance(u, k - done)
+        done = k
+        errs[k] = _compare(host(u), g["steps"][str(k)], idx, G)
+    assert max(errs.values()) < tol, errs
+    return errs
+
+
+@pytest.mark.parametrize("prec,tol", [(P.F64, 1e-10), (P.F32, 1e-8), (P.BF16, 1e-8)])
+def test_config4_fullsize(prec, tol):
+    _run_golden(_load("config4_radau3_1024.json"), P.tableaux.radau_iia(3), prec, P.PC_GS_LOWER, tol)
+
+
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
+def test_config3_fullsize_gl4(pc):
+    _run_golden(_load("config3_gl4_1024.json"), P.tableaux.gauss_legendre(4), P.F64, pc, 1e-10)
+
+
+def test_config2_fullsize_closed_form():
+    N, dt, nsteps = 512, 1e-3, 50
+    u0, amps = synth.sine_modes_u0(N, 0)
+    _, stp = make(N, np.ones(N * N), P.tableaux.radau_iia(3), dt, rtol=1e-10)
+    cf = step.closed_form_modes(N, OT.radau_iia(3), dt, nsteps, amps)
+    u = dev(u0)
+    worst = 0.0
+    for k in range(1, nsteps + 1):
+        stp.advance(u, 1)
+        worst = max(worst, rel(host(u), cf[k]))
+    assert worst < 1e-10, worst
+
+
+def test_config5_fullsize_adjoint():
+    """Adjoint gradient at 512^2, 40 steps, 8 snapshots: against the oracle gradient (1e-8 relative) and central
+    finite differences.
+
+    FD noise: J = 0.025 while |grad.d| ~ 6e-7 for a seeded unit direction d (the gradient is spread over 262,144
+    elements), so J(theta +- h d) differ by ~1e-10 at h = 1e-4. Forward solves at rtol 2e-13 (the attainable
+    FP64 residual of this operator is ~1.1e-13) perturb J by ~5e-14, i.e. ~3e-4 relative noise in the FD of a
+    random direction; along the gradient direction (|grad.d| = |grad| ~ 3e-4) the noise is ~1e-6. Truncation
+    error at h = 1e-4 is far below both."""
+    import torch
+
+    g = _load("config5_adjoint_512.json")
+    N, dt, nsteps = g["N"], g["dt"], g["nsteps"]
+    theta = synth.grf_log_kappa(N, 1)
+    kref = synth.grf_kappa(N, 2)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    tab = P.tableaux.radau_iia(3)
+    opts = {"rtol": 2e-13}
+    # target from the reference diffusivity
+    _, sref = make(N, kref, tab, dt, **opts)
+    ustar = dev(u0)
+    sref.advance(ustar, nsteps)
+
+    def J(th):
+        prob, stp = make(N, np.exp(th), tab, dt, **opts)
+        u = dev(u0)
+        stp.advance(u, nsteps)
+        d = u - ustar
+        return 0.5 * float(torch.dot(d, prob.apply_mass(d))), (prob, stp, u)
+
+    J0, (prob, stp, uN) = J(theta)
+    assert abs(J0 - g["J"]) < 1e-9 * abs(g["J"])
+    lamN = prob.apply_mass(uN - ustar)
+    lam0, grad, st = stp.adjoint(dev(u0), nsteps, 8, lamN)
+    assert st["forward_advances"] == 70  # optimal binomial schedule, 40 steps with 8 snapshots
+    gh = host(grad)
+    idx = np.asarray(g["grad_indices"])
+    G = synth.sketch_vectors(N * N, g["n_sketch"], g["sketch_seed"])
+    assert _compare(gh, g["grad"], idx, G) < 1e-8
+    Gu = synth.sketch_vectors((N - 1) ** 2, g["n_sketch"], g["sketch_seed"])
+    assert _compare(host(lam0), g["lam0"], np.asarray(g["lam0_indices"]), Gu) < 1e-8
+    h = 1e-4
+
+    def fd(d):
+        return (J(theta + h * d)[0] - J(theta - h * d)[0]) / (2 * h)
+
+    dg = gh / np.linalg.norm(gh)
+    assert abs(fd(dg) - gh @ dg) < 1e-5 * abs(gh @ dg)
+    worst = 0.0
+    for d in synth.random_directions(32, N * N, seed=3):
+        worst = max(worst, abs(fd(d) - gh @ d) / abs(gh @ d))
+    assert worst < 5e-3, worst
