@@ -97,14 +97,23 @@ void launch_start_vector(double* x, Geom g, int level, hipStream_t st);
 void launch_scale(double* x, long n, const double* inv_norm2_src, hipStream_t st);
 
 // ---------------------------------------------------------------- multigrid (k_mg.hip)
+// Block Gauss-Seidel coupling folded into the finest-level kernels: their right-hand side becomes
+// t = tscale * v - dt * K * sum_{q<nz} a[q] z_q  (z_q = z + q*zstride, FP64 padded planes).
+struct Couple {
+  const double* z;
+  long zstride;
+  int nz;  // 0: no coupling
+  double dt;
+  double a[kMaxStages];
+};
 // prec: 0 = FP64 storage/compute, 1 = FP32, 2 = BF16 storage / FP32 compute.
 // DOWN: pre-smooth from zero on the fine level, write x, restrict the residual into tc (coarse).
 // t_is_f64: t is the FP64 Krylov vector (scaled by the device scalar *tscale; null = 1) instead of level storage.
 void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, const void* kappa,
-                    Geom g, Geom gc, const MGCoef& c, hipStream_t st);
+                    Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
 // UP: x0 = x + P e, post-smooth, write out (FP64 if out_is_f64).
 void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
-                  const void* kappa, Geom g, Geom gc, const MGCoef& c, hipStream_t st);
+                  const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
 // coarsest level: out = Binv * t on the interior nodes
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
                       hipStream_t st);

@@ -95,16 +95,66 @@ __device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ k
   }
 }
 
-template <typename TV, typename TS, typename TC, int DEG, int TX, int TY>
+
+// Block Gauss-Seidel coupling inside the finest-level tiles: w = sum_q a_q z_q is loaded on the
+// region plus one node (row length RX + 2) together with the other tile loads, staged in LDS,
+// and t -= dt * K w is applied on the region with the region's kappa tile.
+template <typename TC, int RX, int RY>
+struct CoupleLoad {
+  static constexpr int WX = RX + 2, CNT = WX * (RY + 2), NL = (CNT + NT - 1) / NT;
+  TC v[NL];
+  __device__ __forceinline__ void load(const Couple& cp, int ox, int oy, const Geom& g) {
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      const int lj = idx / WX, li = idx - lj * WX;
+      const int i = ox - 1 + li, j = oy - 1 + lj;
+      const bool ok = idx < CNT && interior(i, j, g.N);
+      const long p = ok ? (long)j * g.pitch + i : 0;
+      double acc = 0.0;
+      for (int q = 0; q < cp.nz; ++q) acc += cp.a[q] * cp.z[q * cp.zstride + p];
+      v[r] = ok ? (TC)acc : (TC)0;
+    }
+  }
+  __device__ __forceinline__ void store(TC* sW) const {
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      if (idx < CNT) sW[idx] = v[r];
+    }
+  }
+};
+
+template <typename TC, int RX, int RY, int KX>
+__device__ __forceinline__ void couple_apply(TC* sT, const TC* sW, const TC* sK, const Couple& cp, int ox, int oy,
+                                             const Geom& g) {
+  constexpr int WX = RX + 2;
+  const TC dt = (TC)cp.dt;
+  for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
+    const int lj = idx / RX, li = idx - lj * RX;
+    if (!interior(ox + li, oy + lj, g.N)) continue;
+    const int p = (lj + 1) * WX + (li + 1);
+    const int q = lj * KX + li;
+    const TC kSW = sK[q], kSE = sK[q + 1], kNW = sK[q + KX], kNE = sK[q + KX + 1];
+    const TC Kw = (TC)(2.0 / 3.0) * (kSW + kSE + kNW + kNE) * sW[p] -
+                  (TC)(1.0 / 6.0) * ((kNE + kSE) * sW[p + 1] + (kNW + kSW) * sW[p - 1] + (kNE + kNW) * sW[p + WX] +
+                                     (kSE + kSW) * sW[p - WX]) -
+                  (TC)(1.0 / 3.0) * (kNE * sW[p + WX + 1] + kNW * sW[p + WX - 1] + kSE * sW[p - WX + 1] +
+                                     kSW * sW[p - WX - 1]);
+    sT[idx] -= dt * Kw;
+  }
+}
+
+template <typename TV, typename TS, typename TC, int DEG, int TX, int TY, bool COUPLE>
 __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, const double* __restrict__ tscale, TS* __restrict__ xout,
                                                      TS* __restrict__ tc, const TC* __restrict__ kap, Geom g, Geom gc,
-                                                     MGCoef cf) {
+                                                     MGCoef cf, Couple cp) {
   constexpr int H = DEG + 1;
   constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int KX = RX + 1, KY = RY + 1;
   __shared__ TC sK[KX * KY];
   __shared__ TC sT[RX * RY];
-  __shared__ TC sA[RX * RY];
+  __shared__ TC sA[COUPLE ? (RX + 2) * (RY + 2) : RX * RY];  // also stages the coupling field
   __shared__ TC sB[RX * RY];
   const int N = g.N;
   const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
@@ -123,18 +173,22 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
       const TC val = ld<TC>(t + (ok ? (long)j * g.pitch + i : 0));
       tv[r] = ok ? val * ts : (TC)0;
     }
+    CoupleLoad<TC, RX, RY> w;
+    if (COUPLE) w.load(cp, ox, oy, g);
     load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
       const int idx = threadIdx.x + r * NT;
-      if (idx < CNT) {
-        sT[idx] = tv[r];
-        sA[idx] = (TC)0;
-      }
+      if (idx < CNT) sT[idx] = tv[r];
     }
+    if (COUPLE) w.store(sA);
   }
   __syncthreads();
-  // first Chebyshev step from x0 = 0 is pointwise: x1 = c0 D^{-1} t
+  if (COUPLE) {
+    couple_apply<TC, RX, RY, KX>(sT, sA, sK, cp, ox, oy, g);
+    __syncthreads();
+  }
+  // first Chebyshev step from x0 = 0 is pointwise: x1 = c0 D^{-1} t (x_prev = 0 in sA)
   {
     const TC c0 = (TC)cf.c0;
     for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
@@ -142,6 +196,7 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
       TC v = (TC)0;
       if (interior(ox + li, oy + lj, N)) v = c0 * sT[idx] / diag_at<TC, KX>(sK, li, lj, m, alpha);
       sB[idx] = v;
+      sA[idx] = (TC)0;
     }
   }
   __syncthreads();
@@ -212,17 +267,17 @@ __device__ __forceinline__ TC prolong_at(const TS* __restrict__ e, int pc, int i
   return ((TC)1 - wx) * ((TC)1 - wy) * e00 + wx * ((TC)1 - wy) * e10 + ((TC)1 - wx) * wy * e01 + wx * wy * e11;
 }
 
-template <typename TV, typename TS, typename TC, int DEG, int TX, int TY>
+template <typename TV, typename TS, typename TC, int DEG, int TX, int TY, bool COUPLE>
 __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, const double* __restrict__ tscale, const TS* __restrict__ x,
                                                    const TS* __restrict__ e, TV* __restrict__ out,
-                                                   const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf) {
+                                                   const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf, Couple cp) {
   constexpr int H = DEG;
   constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int KX = RX + 1, KY = RY + 1;
   __shared__ TC sK[KX * KY];
   __shared__ TC sT[RX * RY];
   __shared__ TC sA[RX * RY];
-  __shared__ TC sB[RX * RY];
+  __shared__ TC sB[COUPLE ? (RX + 2) * (RY + 2) : RX * RY];  // also stages the coupling field
   const int N = g.N;
   const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
   const int ox = i0 - H, oy = j0 - H;
@@ -244,6 +299,8 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
       tv[r] = ok ? a : (TC)0;
       xv[r] = ok ? b : (TC)0;
     }
+    CoupleLoad<TC, RX, RY> w;
+    if (COUPLE) w.load(cp, ox, oy, g);
     load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
@@ -251,22 +308,30 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
       if (idx < CNT) {
         sT[idx] = tv[r];
         sA[idx] = xv[r];
-        sB[idx] = (TC)0;
       }
     }
+    if (COUPLE) w.store(sB);
   }
   __syncthreads();
-  // first step from the corrected x0: x1 = x0 + c0 D^{-1} (t - B x0)
+  if (COUPLE) {
+    couple_apply<TC, RX, RY, KX>(sT, sB, sK, cp, ox, oy, g);
+    __syncthreads();
+  }
+  // first step from the corrected x0: x1 = x0 + c0 D^{-1} (t - B x0), written on the whole
+  // inner region (zero outside the domain); the region's edge ring of sB is never read again
   {
     const TC c0 = (TC)cf.c0;
     const int w = RX - 2, hgt = RY - 2;
     for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
       const int lj = 1 + idx / w, li = 1 + idx % w;
-      if (!interior(ox + li, oy + lj, N)) continue;
-      TC Bx, D;
-      bx_d<TC, RX, KX>(sA, sK, li, lj, m, alpha, Bx, D);
       const int p = lj * RX + li;
-      sB[p] = sA[p] + c0 * (sT[p] - Bx) / D;
+      TC v = (TC)0;
+      if (interior(ox + li, oy + lj, N)) {
+        TC Bx, D;
+        bx_d<TC, RX, KX>(sA, sK, li, lj, m, alpha, Bx, D);
+        v = sA[p] + c0 * (sT[p] - Bx) / D;
+      }
+      sB[p] = v;
     }
   }
   __syncthreads();
@@ -296,101 +361,122 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
   }
 }
 
-// Coarsest level: out = Binv * t on the n = (N-1)^2 interior nodes. One wavefront per
-// row (lanes stride the row, coalesced), the compacted right-hand side staged in LDS by
-// every block, a fixed-order wavefront reduction per row.
+// Coarsest level: out = Binv * t on the n = (N-1)^2 <= 1024 interior nodes. One wavefront per
+// row; each lane issues all of its (at most 16) coalesced row loads and right-hand-side loads
+// before accumulating, then a fixed-order wavefront reduction.
 template <typename TI, typename TO, typename TC>
 __global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t, const double* __restrict__ tscale,
                                                        TO* __restrict__ out, const TC* __restrict__ Binv, Geom g) {
-  __shared__ TC sv[kMaxCoarse];
   const int m = g.N - 1;
   const int n = m * m;
-  const TC tsc = tscale ? (TC)(*tscale) : (TC)1;
-  for (int q = threadIdx.x; q < n; q += NT) {
-    const int j = q / m + 1, i = q % m + 1;
-    sv[q] = ld<TC>(t + (long)j * g.pitch + i) * tsc;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (row >= n) return;
   const TC* r = Binv + (long)row * n;
+  constexpr int U = kMaxCoarse / 64;
+  TC bv[U], tv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int c = lane + 64 * u;
+    const int cc = c < n ? c : 0;
+    const int j = cc / m + 1, i = cc - (j - 1) * m + 1;
+    bv[u] = r[cc];
+    tv[u] = ld<TC>(t + (long)j * g.pitch + i);
+  }
   TC acc = (TC)0;
-  for (int c = lane; c < n; c += 64) acc += r[c] * sv[c];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (lane + 64 * u < n) acc += bv[u] * tv[u];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
+    const TC tsc = tscale ? (TC)(*tscale) : (TC)1;
     const int j = row / m + 1, i = row % m + 1;
-    st(out + (long)j * g.pitch + i, acc);
+    st(out + (long)j * g.pitch + i, acc * tsc);
   }
 }
 
 constexpr int TXD = 64, TYD = 16;
 
+template <typename TV, typename TS, typename TC, bool CP>
+void down_launch(const TV* tt, const double* tscale, TS* xx, TS* cc, const TC* kk, Geom g, Geom gc, const MGCoef& c,
+                 const Couple& cp, hipStream_t st) {
+  const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
+  switch (c.deg) {
+    case 1: mg_down_kernel<TV, TS, TC, 1, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
+    case 2: mg_down_kernel<TV, TS, TC, 2, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
+    default:
+      mg_down_kernel<TV, TS, TC, 3, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp);
+      break;
+  }
+}
+
 template <typename TV, typename TS, typename TC>
 void down_t(const void* t, const double* tscale, void* x, void* tc, const void* kap, Geom g, Geom gc, const MGCoef& c,
-            hipStream_t st) {
+            const Couple& cp, hipStream_t st) {
+  if (cp.nz > 0)
+    down_launch<TV, TS, TC, true>((const TV*)t, tscale, (TS*)x, (TS*)tc, (const TC*)kap, g, gc, c, cp, st);
+  else
+    down_launch<TV, TS, TC, false>((const TV*)t, tscale, (TS*)x, (TS*)tc, (const TC*)kap, g, gc, c, cp, st);
+}
+
+template <typename TV, typename TS, typename TC, bool CP>
+void up_launch(const TV* tt, const double* tscale, const TS* xx, const TS* ee, TV* oo, const TC* kk, Geom g, Geom gc,
+               const MGCoef& c, const Couple& cp, hipStream_t st) {
   const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
-  const TV* tt = (const TV*)t;
-  TS* xx = (TS*)x;
-  TS* cc = (TS*)tc;
-  const TC* kk = (const TC*)kap;
   switch (c.deg) {
-    case 1: mg_down_kernel<TV, TS, TC, 1, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c); break;
-    case 2: mg_down_kernel<TV, TS, TC, 2, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c); break;
-    default: mg_down_kernel<TV, TS, TC, 3, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c); break;
+    case 1: mg_up_kernel<TV, TS, TC, 1, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
+    case 2: mg_up_kernel<TV, TS, TC, 2, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
+    default:
+      mg_up_kernel<TV, TS, TC, 3, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp);
+      break;
   }
 }
 
 template <typename TV, typename TS, typename TC>
 void up_t(const void* t, const double* tscale, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
-          const MGCoef& c, hipStream_t st) {
-  const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
-  const TV* tt = (const TV*)t;
-  const TS* xx = (const TS*)x;
-  const TS* ee = (const TS*)e;
-  TV* oo = (TV*)out;
-  const TC* kk = (const TC*)kap;
-  switch (c.deg) {
-    case 1: mg_up_kernel<TV, TS, TC, 1, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c); break;
-    case 2: mg_up_kernel<TV, TS, TC, 2, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c); break;
-    default: mg_up_kernel<TV, TS, TC, 3, TXD, TYD><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c); break;
-  }
+          const MGCoef& c, const Couple& cp, hipStream_t st) {
+  if (cp.nz > 0)
+    up_launch<TV, TS, TC, true>((const TV*)t, tscale, (const TS*)x, (const TS*)e, (TV*)out, (const TC*)kap, g, gc, c, cp,
+                                st);
+  else
+    up_launch<TV, TS, TC, false>((const TV*)t, tscale, (const TS*)x, (const TS*)e, (TV*)out, (const TC*)kap, g, gc, c,
+                                 cp, st);
 }
 
 }  // namespace
 
 void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, const void* kappa,
-                    Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
+                    Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st) {
   if (prec == 0) {
-    down_t<double, double, double>(t, tscale, x, tc, kappa, g, gc, c, st);
+    down_t<double, double, double>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
   } else if (prec == 1) {
     if (t_is_f64)
-      down_t<double, float, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+      down_t<double, float, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
     else
-      down_t<float, float, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+      down_t<float, float, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
   } else {
     if (t_is_f64)
-      down_t<double, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+      down_t<double, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
     else
-      down_t<bf16, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, st);
+      down_t<bf16, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
   }
 }
 
 void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
-                  const void* kappa, Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
+                  const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st) {
   if (prec == 0) {
-    up_t<double, double, double>(t, tscale, x, e, out, kappa, g, gc, c, st);
+    up_t<double, double, double>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
   } else if (prec == 1) {
     if (io_is_f64)
-      up_t<double, float, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+      up_t<double, float, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
     else
-      up_t<float, float, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+      up_t<float, float, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
   } else {
     if (io_is_f64)
-      up_t<double, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+      up_t<double, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
     else
-      up_t<bf16, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, st);
+      up_t<bf16, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
   }
 }
 

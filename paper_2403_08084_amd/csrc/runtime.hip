@@ -410,8 +410,11 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
 // ------------------------------------------------------------------ preconditioner
 
 // out = one V-cycle for block `stage` applied to tscale * t (FP64 padded planes)
-int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, double* out, hipStream_t s) {
+int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, double* out, hipStream_t s,
+           const Couple* cpl = nullptr) {
   const int L = (int)st->lv.size();
+  Couple none{};
+  const Couple& cp = cpl ? *cpl : none;
   const MGCoef* cf = &st->coef[(size_t)stage * L];
   const int pr = st->prec;
   if (L == 1) {
@@ -419,13 +422,15 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
     return check_launch();
   }
   std::vector<Level>& lv = st->lv;
-  launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
+  launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
   for (int l = 1; l < L - 1; ++l)
-    launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+    launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], none,
+                   s);
   launch_mg_coarse(pr, false, lv[L - 1].t, nullptr, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
   for (int l = L - 2; l >= 1; --l)
-    launch_mg_up(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
-  launch_mg_up(pr, true, t, tscale, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
+    launch_mg_up(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l],
+                 none, s);
+  launch_mg_up(pr, true, t, tscale, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
   return check_launch();
 }
 
@@ -437,11 +442,22 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
     const double* vi = v + i * plane;
     double* zi = z + i * plane;
     if (st->opt.precond == IRK_PC_GS_LOWER && i > 0) {
-      Coefs row{};
-      for (int j = 0; j < i; ++j) row.a[j] = a.a[i * kMaxStages + j];
-      double* t = st->tmp2;
-      launch_gs_couple(vi, vscale, z, i, row, st->dt, st->prob->kappa, t, st->g, s);
-      CHK(vcycle(st, i, t, nullptr, zi, s));
+      if (st->lv.size() > 1) {
+        // the coupling -dt K sum_{j<i} a_ij z_j is formed inside the finest-level kernels
+        Couple cp{};
+        cp.z = z;
+        cp.zstride = plane;
+        cp.nz = i;
+        cp.dt = st->dt;
+        for (int j = 0; j < i; ++j) cp.a[j] = a.a[i * kMaxStages + j];
+        CHK(vcycle(st, i, vi, vscale, zi, s, &cp));
+      } else {
+        Coefs row{};
+        for (int j = 0; j < i; ++j) row.a[j] = a.a[i * kMaxStages + j];
+        double* t = st->tmp2;
+        launch_gs_couple(vi, vscale, z, i, row, st->dt, st->prob->kappa, t, st->g, s);
+        CHK(vcycle(st, i, t, nullptr, zi, s));
+      }
     } else {
       CHK(vcycle(st, i, vi, vscale, zi, s));
     }
