@@ -2,17 +2,19 @@
 
 Test infrastructure only (see the package docstring).
 
-Section 3.1 (Block preconditioners) splits the Butcher matrix A = L + D + U and
-replaces A by D (block Jacobi, eq:pcbjac) or by L + D (block Gauss-Seidel,
-eq:pcbgs). The paper states both for the form eq:block_struct_IA and notes that
+Section 3.1 (Block preconditioners) replaces the Butcher matrix A by a lower
+triangular Atil: with the additive split A = L + D + U, Atil = D (block Jacobi,
+eq:pcbjac) or L + D (block Gauss-Seidel, eq:pcbgs); with the multiplicative
+factorisation A = L_1 D U_1 (unit triangular L_1, U_1), Atil = L_1 D (Rana-LD,
+eq:pcranald). The paper states them for the form eq:block_struct_IA and notes that
 the form eq:block_struct_AI "follows similarly"; the reading used here (the AI
 form) is
 
-    P_D = I (x) M + dt * D (x) K,         P_L = I (x) M + dt * (L + D) (x) K.
+    P = I (x) M + dt * Atil (x) K.
 
-Applying P_L^{-1} to v is block forward substitution:
-    t_i = v_i - dt * K * sum_{j<i} a_ij z_j,    z_i = B_i^{-1} t_i,
-with the diagonal blocks B_i = M + dt * a_ii * K (the backward-Euler-like blocks
+Applying P^{-1} to v is block forward substitution:
+    t_i = v_i - dt * K * sum_{j<i} atil_ij z_j,    z_i = B_i^{-1} t_i,
+with the diagonal blocks B_i = M + dt * atil_ii * K (the backward-Euler-like blocks
 of Section 3.1, there written a_jj^{-1} M + dt K for the IA form). The paper
 approximates B_i^{-1} by multigrid; this module states the geometric multigrid
 V-cycle used for that:
@@ -204,38 +206,73 @@ class Hierarchy:
         return x
 
 
-def apply_block_preconditioner(kind, A, dt, K, v, block_solve):
-    """Apply P^{-1} for the AI-form stage preconditioner.
-
-    kind: "jacobi" (P_D) or "gs_lower" (P_L). v is stage-major (s*n,).
-    block_solve(i, t) must return (an approximation of) B_i^{-1} t with
-    B_i = M + dt*a_ii*K.
-    """
-    A = np.asarray(A)
+def ldu(A):
+    """A = L1 diag(D) U1 with unit lower L1 and unit upper U1 (Gaussian elimination without pivoting)."""
+    A = np.asarray(A, dtype=np.float64)
     s = A.shape[0]
+    L1, U1, D = np.eye(s), np.eye(s), np.zeros(s)
+    W = A.copy()
+    for k in range(s):
+        D[k] = W[k, k]
+        if D[k] == 0.0:
+            raise ValueError("zero pivot: A has no LDU factorisation without pivoting")
+        for i in range(k + 1, s):
+            L1[i, k] = W[i, k] / D[k]
+            U1[k, i] = W[k, i] / D[k]
+        for i in range(k + 1, s):
+            for j in range(k + 1, s):
+                W[i, j] -= L1[i, k] * D[k] * U1[k, j]
+    return L1, D, U1
+
+
+def preconditioner_matrix(kind, A):
+    """Atil of the stage preconditioner: D, L + D, or L1 D (Section 3.1)."""
+    A = np.asarray(A, dtype=np.float64)
+    if kind == "jacobi":
+        return np.diag(np.diag(A))
+    if kind == "gs_lower":
+        return np.tril(A)
+    if kind == "rana_ld":
+        L1, D, _ = ldu(A)
+        return L1 @ np.diag(D)
+    raise ValueError(kind)
+
+
+def apply_block_preconditioner(kind, A, dt, K, v, block_solve):
+    """Apply P^{-1} for the AI-form stage preconditioner P = I (x) M + dt Atil (x) K.
+
+    kind: "jacobi" (P_D), "gs_lower" (P_L) or "rana_ld" (P_LD); v is stage-major (s*n,).
+    block_solve(i, t) must return (an approximation of) B_i^{-1} t with
+    B_i = M + dt*atil_ii*K.
+    """
+    Atil = preconditioner_matrix(kind, A)
+    s = Atil.shape[0]
     V = np.asarray(v).reshape(s, -1)
     Z = np.zeros_like(V)
     for i in range(s):
         t = V[i].copy()
-        if kind == "gs_lower":
+        if i > 0 and kind != "jacobi":
             w = np.zeros_like(t)
             for j in range(i):
-                w += A[i, j] * Z[j]
+                w += Atil[i, j] * Z[j]
             t = t - dt * (K @ w)
-        elif kind != "jacobi":
-            raise ValueError(kind)
         Z[i] = block_solve(i, t)
     return Z.ravel()
 
 
+def _diagonal(A):
+    A = np.asarray(A, dtype=np.float64)
+    return np.diag(A) if A.ndim == 2 else A
+
+
 def exact_block_solver(M, K, A, dt):
-    """block_solve that inverts every diagonal block B_i exactly (sparse LU)."""
-    A = np.asarray(A)
-    lus = [spla.splu((M + dt * A[i, i] * K).tocsc()) for i in range(A.shape[0])]
+    """block_solve inverting every diagonal block M + dt*d_i*K exactly (sparse LU); A is Atil or its diagonal."""
+    d = _diagonal(A)
+    lus = [spla.splu((M + dt * d[i] * K).tocsc()) for i in range(d.size)]
     return lambda i, t: lus[i].solve(t)
 
 
 def vcycle_block_solver(hier: Hierarchy, A):
-    """block_solve that applies one V-cycle of `hier` to every diagonal block."""
-    A = np.asarray(A)
-    return lambda i, t: hier.vcycle(A[i, i], t)
+    """block_solve applying one V-cycle of `hier` to every diagonal block; A is Atil or its diagonal."""
+    d = _diagonal(A)
+    return lambda i, t: hier.vcycle(d[i], t)

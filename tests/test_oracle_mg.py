@@ -124,16 +124,33 @@ def _block_prec_matrix(M, K, Atil, dt):
     return step.coupled_matrix(M, K, Atil, dt)
 
 
-@pytest.mark.parametrize("kind", ["jacobi", "gs_lower"])
+def test_ldu_factorisation():
+    for A in (T.radau_iia(3)["A"], T.gauss_legendre(4)["A"], T.lobatto_iiic2()["A"]):
+        L1, D, U1 = mg.ldu(A)
+        assert np.abs(L1 @ np.diag(D) @ U1 - A).max() < 1e-15
+        assert np.array_equal(np.diag(L1), np.ones(len(D))) and np.array_equal(np.diag(U1), np.ones(len(D)))
+        assert np.abs(np.triu(L1, 1)).max() == 0 and np.abs(np.tril(U1, -1)).max() == 0
+        assert np.all(D > 0)
+    # a lower-triangular A (a DIRK) is its own L1 D, so Rana-LD reproduces the stage operator
+    A = T.alexander()["A"]
+    assert np.abs(mg.preconditioner_matrix("rana_ld", A) - A).max() < 1e-15
+    # first pivot and the 2x2 Schur complement by hand
+    A2 = np.array([[2.0, 1.0], [4.0, 5.0]])
+    L1, D, U1 = mg.ldu(A2)
+    assert D[0] == 2.0 and D[1] == 5.0 - 4.0 * 1.0 / 2.0 and L1[1, 0] == 2.0 and U1[0, 1] == 0.5
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "gs_lower", "rana_ld"])
 def test_exact_block_preconditioner_definition(kind):
-    # with exact blocks, P^{-1} v solves I (x) M + dt Atil (x) K with Atil = D or L + D
+    # with exact blocks, P^{-1} v solves I (x) M + dt Atil (x) K with Atil = D, L + D or L1 D
     N, dt = 10, 1e-2
     kap = synth.grf_kappa(N, 4)
     M, K = fem.assemble(N, kap)
     A = T.radau_iia(3)["A"]
-    Atil = np.diag(np.diag(A)) if kind == "jacobi" else np.tril(A)
+    L1, D, U1 = mg.ldu(A)
+    Atil = {"jacobi": np.diag(np.diag(A)), "gs_lower": np.tril(A), "rana_ld": L1 @ np.diag(D)}[kind]
     v = np.random.default_rng(5).standard_normal(3 * (N - 1) ** 2)
-    z = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.exact_block_solver(M, K, A, dt))
+    z = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.exact_block_solver(M, K, Atil, dt))
     P = _block_prec_matrix(M, K, Atil, dt)
     assert np.linalg.norm(P @ z - v) < 1e-12 * np.linalg.norm(v)
 
