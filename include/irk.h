@@ -16,10 +16,11 @@
  * and invertible A make every stage vanish on the boundary.
  *
  * The system is solved by right-preconditioned FGMRES. The preconditioner is the
- * block Jacobi (eq:pcbjac) or block lower Gauss-Seidel (eq:pcbgs) stage
- * preconditioner, in the AI form  I (x) M + dt * Atil (x) K  with Atil = D or
- * L + D of A = L + D + U; each diagonal block M + dt*a_ii*K is approximated by one
- * geometric multigrid V-cycle (Section 3.1).
+ * block Jacobi (eq:pcbjac), block lower Gauss-Seidel (eq:pcbgs) or Rana-LD
+ * (eq:pcranald) stage preconditioner, in the AI form  I (x) M + dt * Atil (x) K  with
+ * Atil = D or L + D of A = L + D + U, or Atil = L1 D of A = L1 D U1 (unit triangular
+ * L1, U1); each diagonal block M + dt*atil_ii*K is approximated by one geometric
+ * multigrid V-cycle (Section 3.1).
  *
  * Conventions for every entry point:
  *  - Return value: IRK_OK (0) or a negative irk_status. After an error,
@@ -56,7 +57,7 @@ typedef enum {
   IRK_EBREAKDOWN = -5   /* non-finite value met inside the Krylov iteration    */
 } irk_status;
 
-enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1 };            /* eq:pcbjac, eq:pcbgs */
+enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2 };  /* eq:pcbjac, eq:pcbgs, eq:pcranald */
 enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precision */
 enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1 };    /* Gram-Schmidt variant */
 enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial guess */
@@ -72,7 +73,7 @@ typedef struct {
 
 /* Solver options; fill with irk_options_default() and override fields. */
 typedef struct {
-  int precond;        /* IRK_PC_JACOBI or IRK_PC_GS_LOWER                         */
+  int precond;        /* IRK_PC_JACOBI, IRK_PC_GS_LOWER or IRK_PC_RANA_LD          */
   double rtol;        /* stop when |f - Acal k|_2 <= rtol * |f|_2 (true residual)  */
   int restart;        /* FGMRES restart length m, 1..32                           */
   int max_it;         /* total FGMRES iterations allowed per stage solve          */
@@ -129,7 +130,8 @@ int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *
  * multigrid hierarchy (level diffusivities, power-iteration estimates of mu per
  * level and diagonal block, the coarsest-level inverse) and the Krylov
  * workspace. Every eigenvalue of A must have positive real part and every
- * a_ii > 0 (IRK_EINVAL otherwise). The problem must outlive the stepper. */
+ * a_ii > 0 (Rana-LD: every LDU pivot > 0) (IRK_EINVAL otherwise). The problem must
+ * outlive the stepper. */
 int irk_stepper_create(irk_stepper **out, const irk_problem *p, const irk_tableau *tab,
                        double dt, const irk_options *opts, void *stream);
 void irk_stepper_destroy(irk_stepper *st);
@@ -142,12 +144,14 @@ int irk_stage_rhs(const irk_stepper *st, const double *u, const double *F, doubl
  * x, y: device s*n, no overlap. */
 int irk_apply_stage_operator(const irk_stepper *st, const double *x, double *y, int transpose, void *stream);
 
-/* a3 (eq:pcbjac / eq:pcbgs, AI form): z = P^{-1} v with the stepper's block preconditioner,
- * every diagonal block solve replaced by one V-cycle. v, z: device s*n. */
+/* a3 (eq:pcbjac / eq:pcbgs / eq:pcranald, AI form): z = P^{-1} v with the stepper's block
+ * preconditioner, every diagonal block solve replaced by one V-cycle. With transpose != 0 the
+ * preconditioner of the transposed system (built from A^T) is applied. v, z: device s*n. */
 int irk_apply_preconditioner(const irk_stepper *st, const double *v, double *z, int transpose, void *stream);
 
-/* a4 (Section 3.1 diagonal blocks): z = one V-cycle for (M + dt*a_ii*K) z = t with zero
- * initial guess, for stage `stage` (0-based). t, z: device n. */
+/* a4 (Section 3.1 diagonal blocks): z = one V-cycle for (M + dt*atil_ii*K) z = t with zero
+ * initial guess, for stage `stage` (0-based; atil_ii = a_ii, or the LDU pivot for Rana-LD).
+ * t, z: device n. */
 int irk_vcycle(const irk_stepper *st, int stage, const double *t, double *z, void *stream);
 
 /* a5: solve (I (x) M + dt*A (x) K) k = f (A^T when transpose != 0) by FGMRES to the

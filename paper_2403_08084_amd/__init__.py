@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libirk.so")
 
 IRK_OK, IRK_EINVAL, IRK_ENOMEM, IRK_EHIP, IRK_ENOCONV, IRK_EBREAKDOWN = 0, -1, -2, -3, -4, -5
-PC_JACOBI, PC_GS_LOWER = 0, 1
+PC_JACOBI, PC_GS_LOWER, PC_RANA_LD = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 ORTH_CGS2, ORTH_CGS_SELECTIVE = 0, 1
 GUESS_ZERO, GUESS_PREV = 0, 1

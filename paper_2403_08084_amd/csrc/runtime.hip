@@ -91,6 +91,10 @@ struct irk_stepper {
   double b[kMaxStages] = {};
   double c[kMaxStages] = {};
   double dt = 0;
+  // preconditioner matrix Atil (lower triangular, row-major) for the forward [0] and transposed [1]
+  // systems, and its diagonal (the diagonal blocks M + dt*pd_i*K)
+  double Pt[2][kMaxStages * kMaxStages] = {};
+  double pd[kMaxStages] = {};
   irk_options opt{};
   int prec = 0;
   Geom g{};
@@ -136,6 +140,13 @@ Coefs coefs_of(const irk_stepper* st, bool trans) {
   Coefs a{};
   for (int i = 0; i < st->s; ++i)
     for (int j = 0; j < st->s; ++j) a.a[i * kMaxStages + j] = trans ? st->A[j * st->s + i] : st->A[i * st->s + j];
+  return a;
+}
+
+Coefs ptil_of(const irk_stepper* st, bool trans) {
+  Coefs a{};
+  for (int i = 0; i < st->s; ++i)
+    for (int j = 0; j < st->s; ++j) a.a[i * kMaxStages + j] = st->Pt[trans ? 1 : 0][i * st->s + j];
   return a;
 }
 
@@ -366,7 +377,7 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
   st->coef.assign((size_t)st->s * L, MGCoef{});
   st->mu.assign((size_t)st->s * L, 0.0);
   for (int i = 0; i < st->s; ++i) {
-    const double alpha = st->dt * st->A[i * st->s + i];
+    const double alpha = st->dt * st->pd[i];
     for (int l = 0; l < L; ++l) {
       MGCoef& c = st->coef[(size_t)i * L + l];
       c.alpha = alpha;
@@ -376,7 +387,7 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
         // reuse the estimate of an earlier stage with the same diagonal entry
         double mu = 0;
         for (int i2 = 0; i2 < i; ++i2)
-          if (st->A[i2 * st->s + i2] == st->A[i * st->s + i]) mu = st->mu[(size_t)i2 * L + l];
+          if (st->pd[i2] == st->pd[i]) mu = st->mu[(size_t)i2 * L + l];
         if (mu == 0) CHK(power_mu(st, l, alpha, &mu, s));
         st->mu[(size_t)i * L + l] = mu;
         cheb_coef(mu, st->opt, c);
@@ -394,7 +405,7 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
   const int nc = (lc.g.N - 1) * (lc.g.N - 1);
   for (int i = 0; i < st->s; ++i) {
     std::vector<double> inv;
-    CHK(coarse_inverse(kc, lc.g.N, st->dt * st->A[i * st->s + i], inv));
+    CHK(coarse_inverse(kc, lc.g.N, st->dt * st->pd[i], inv));
     if (st->prec == 0) {
       CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(double)));
       HIPCHK(hipMemcpy(st->binv[i], inv.data(), (size_t)nc * nc * sizeof(double), hipMemcpyHostToDevice));
@@ -437,11 +448,11 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
 // z = P^{-1} (vscale * v), block Jacobi or block lower Gauss-Seidel in the AI form (vscale: device scalar or null)
 int precondition(irk_stepper* st, const double* v, const double* vscale, double* z, bool trans, hipStream_t s) {
   const long plane = st->g.plane;
-  const Coefs a = coefs_of(st, trans);
+  const Coefs a = ptil_of(st, trans);
   for (int i = 0; i < st->s; ++i) {
     const double* vi = v + i * plane;
     double* zi = z + i * plane;
-    if (st->opt.precond == IRK_PC_GS_LOWER && i > 0) {
+    if (st->opt.precond != IRK_PC_JACOBI && i > 0) {
       if (st->lv.size() > 1) {
         // the coupling -dt K sum_{j<i} a_ij z_j is formed inside the finest-level kernels
         Couple cp{};
@@ -928,7 +939,8 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   irk_options o;
   irk_options_default(&o);
   if (opts) o = *opts;
-  if (o.precond != IRK_PC_JACOBI && o.precond != IRK_PC_GS_LOWER) return fail(IRK_EINVAL, "unknown precond");
+  if (o.precond != IRK_PC_JACOBI && o.precond != IRK_PC_GS_LOWER && o.precond != IRK_PC_RANA_LD)
+    return fail(IRK_EINVAL, "unknown precond");
   if (o.restart < 1 || o.restart > 32) return fail(IRK_EINVAL, "restart must be in 1..32");
   if (o.max_it < 1) return fail(IRK_EINVAL, "max_it must be >= 1");
   if (!(o.rtol > 0) || !(o.rtol < 1)) return fail(IRK_EINVAL, "rtol must be in (0, 1)");
@@ -959,6 +971,45 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   }
   st->dt = dt;
   st->opt = o;
+  {
+    // Atil: D, L + D (additive split, eq:pcbjac / eq:pcbgs) or L1 D of A = L1 D U1 (eq:pcranald);
+    // the transposed system A^T uses D, tril(A^T), or U1^T D (A^T = U1^T D L1^T has the same D)
+    double L1[kMaxStages * kMaxStages] = {}, U1[kMaxStages * kMaxStages] = {}, D[kMaxStages] = {};
+    if (o.precond == IRK_PC_RANA_LD) {
+      double W[kMaxStages * kMaxStages];
+      for (int i = 0; i < s * s; ++i) W[i] = tab->A[i];
+      for (int k = 0; k < s; ++k) {
+        D[k] = W[k * s + k];
+        if (!(D[k] > 0)) {
+          delete st;
+          return fail(IRK_EINVAL, "Rana-LD needs A = L D U with positive pivots D");
+        }
+        L1[k * s + k] = U1[k * s + k] = 1.0;
+        for (int i = k + 1; i < s; ++i) {
+          L1[i * s + k] = W[i * s + k] / D[k];
+          U1[k * s + i] = W[k * s + i] / D[k];
+        }
+        for (int i = k + 1; i < s; ++i)
+          for (int j = k + 1; j < s; ++j) W[i * s + j] -= L1[i * s + k] * D[k] * U1[k * s + j];
+      }
+    }
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        double f = 0, t = 0;
+        if (o.precond == IRK_PC_JACOBI) {
+          f = t = (i == j) ? tab->A[i * s + i] : 0.0;
+        } else if (o.precond == IRK_PC_GS_LOWER) {
+          f = (j <= i) ? tab->A[i * s + j] : 0.0;
+          t = (j <= i) ? tab->A[j * s + i] : 0.0;
+        } else {
+          f = (j <= i) ? L1[i * s + j] * D[j] : 0.0;
+          t = (j <= i) ? U1[j * s + i] * D[j] : 0.0;
+        }
+        st->Pt[0][i * s + j] = f;
+        st->Pt[1][i * s + j] = t;
+      }
+    for (int i = 0; i < s; ++i) st->pd[i] = st->Pt[0][i * s + i];
+  }
   st->prec = o.mg_precision;
   st->g = p->g;
   st->vlen = (long)s * p->g.plane;

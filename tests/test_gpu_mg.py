@@ -56,17 +56,28 @@ def test_vcycle_contracts():
         e = e2
 
 
-@pytest.mark.parametrize("kind,pc", [("jacobi", P.PC_JACOBI), ("gs_lower", P.PC_GS_LOWER)])
+@pytest.mark.parametrize("kind,pc", [("jacobi", P.PC_JACOBI), ("gs_lower", P.PC_GS_LOWER),
+                                     ("rana_ld", P.PC_RANA_LD)])
 @pytest.mark.parametrize("transpose", [False, True])
-def test_block_preconditioner(kind, pc, transpose):
-    N, dt = 96, 1e-3
+@pytest.mark.parametrize("tname,N", [("radau3", 96), ("gl4", 64), ("radau2", 33)])
+def test_block_preconditioner(kind, pc, transpose, tname, N):
+    # N = 33 is odd: a single level, the coupling is formed by its own kernel instead of the finest MG kernels
+    dt = 1e-3
     kap = synth.grf_kappa(N, 3)
     M, K = fem.assemble(N, kap)
-    otab = OT.radau_iia(3)
+    otab = {"radau3": OT.radau_iia(3), "gl4": OT.gauss_legendre(4), "radau2": OT.radau_iia(2)}[tname]
+    ptab = {"radau3": P.tableaux.radau_iia(3), "gl4": P.tableaux.gauss_legendre(4),
+            "radau2": P.tableaux.radau_iia(2)}[tname]
+    s = otab["A"].shape[0]
     A = otab["A"].T if transpose else otab["A"]
+    Atil = mg.preconditioner_matrix(kind, A)
     hier = mg.Hierarchy(N, kap, dt)
-    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=pc)
-    v = synth.random_stage_block(N, 3, 11).ravel()
+    _, stp = make(N, kap, ptab, dt, precond=pc)
+    for i in range(s):
+        # each stage's V-cycle approximates M + dt * atil_ii * K (the LDU pivot for Rana-LD)
+        t = synth.random_stage_block(N, 1, 12 + i).ravel()
+        assert rel(host(stp.vcycle(i, dev(t))), hier.vcycle(Atil[i, i], t)) < 1e-12
+    v = synth.random_stage_block(N, s, 11).ravel()
     z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
-    ref = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.vcycle_block_solver(hier, A))
+    ref = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.vcycle_block_solver(hier, Atil))
     assert rel(z, ref) < 1e-12

@@ -16,7 +16,7 @@ def _max_rel(gpu_list, ora_list):
     return max(rel(a, b) for a, b in zip(gpu_list, ora_list))
 
 
-@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER, P.PC_RANA_LD])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_solve_stages_matches_direct(pc, transpose):
     N, dt = 64, 1e-3
@@ -66,7 +66,7 @@ def test_config2_shape_closed_form(N):
     assert _max_rel(gpu, cf) < 1e-10
 
 
-@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER, P.PC_RANA_LD])
 def test_config3_shape_gl4(pc):
     # variable kappa (GRF), Gauss-Legendre(4), dt = 5e-4; direct coupled oracle
     N, dt, nsteps = 128, 5e-4, 4
@@ -142,6 +142,36 @@ def test_iterations_grow_with_stages_and_gs_beats_jacobi():
     assert its[(P.PC_JACOBI, 3)] > its[(P.PC_JACOBI, 1)]
     assert its[(P.PC_GS_LOWER, 3)] > its[(P.PC_GS_LOWER, 1)]
     assert its[(P.PC_GS_LOWER, 3)] < its[(P.PC_JACOBI, 3)]
+
+
+def test_rana_ld_iterations_flat_in_stages():
+    # paper's trend (Section 4.1 heat study): P_LD iteration counts stay nearly flat over the number of
+    # stages while P_L's grow; P_LD needs no more iterations than P_L
+    N, dt = 128, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    its = {}
+    for pc in (P.PC_GS_LOWER, P.PC_RANA_LD):
+        for s in (1, 2, 3, 4):
+            _, stp = make(N, kap, P.tableaux.radau_iia(s), dt, precond=pc, rtol=1e-10)
+            u = dev(u0)
+            _, st = stp.advance(u, 2)
+            its[(pc, s)] = st["fgmres_its_total"] / 2
+    print(its)
+    for s in (2, 3, 4):
+        assert its[(P.PC_RANA_LD, s)] <= its[(P.PC_GS_LOWER, s)]
+    assert its[(P.PC_RANA_LD, 1)] == its[(P.PC_GS_LOWER, 1)]
+    assert its[(P.PC_RANA_LD, 4)] - its[(P.PC_RANA_LD, 1)] < its[(P.PC_GS_LOWER, 4)] - its[(P.PC_GS_LOWER, 1)]
+
+
+def test_rana_ld_rejects_nonpositive_pivot():
+    # A = [[1, 2], [2, 1]] has a_ii > 0 but the second LDU pivot is 1 - 4 = -3
+    N = 16
+    prob = P.Problem(N, dev(np.ones(N * N)))
+    tab = {"A": np.array([[1.0, 2.0], [2.0, 1.0]]), "b": np.array([0.5, 0.5]), "c": np.array([3.0, 3.0])}
+    with pytest.raises(P.IrkError) as e:
+        P.Stepper(prob, tab, 1e-3, precond=P.PC_RANA_LD)
+    assert e.value.code == P.IRK_EINVAL
 
 
 def test_enoconv_keeps_last_good_state():
