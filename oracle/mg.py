@@ -175,13 +175,14 @@ class Hierarchy:
                 kap = coarsen_kappa(Nl, kap)
         self._blocks = {}
 
-    def block(self, a: float):
-        """Per-level operators for one diagonal block B(a): (B, Dinv, mu) lists and the coarse Cholesky factor."""
-        key = float(a)
+    def block(self, a: float, c: float = 1.0):
+        """Per-level operators for one diagonal block B = c*M + dt*a*K: (B, Dinv, mu) lists and the coarse
+        Cholesky factor. c = 1 is the AI-form block; c = 1/atil_ii, a = 1 the IA-form block."""
+        key = (float(a), float(c))
         if key not in self._blocks:
             Bs, Dinvs, mus = [], [], []
             for l in range(len(self.sizes)):
-                B = (self.M[l] + self.dt * a * self.K[l]).tocsr()
+                B = (c * self.M[l] + self.dt * a * self.K[l]).tocsr()
                 Dinv = 1.0 / B.diagonal()
                 Bs.append(B)
                 Dinvs.append(Dinv)
@@ -190,9 +191,9 @@ class Hierarchy:
             self._blocks[key] = (Bs, Dinvs, mus, chol)
         return self._blocks[key]
 
-    def vcycle(self, a: float, t: np.ndarray, level: int = 0) -> np.ndarray:
-        """One V-cycle for B(a) x = t with zero initial guess on `level`."""
-        Bs, Dinvs, mus, chol = self.block(a)
+    def vcycle(self, a: float, t: np.ndarray, level: int = 0, c: float = 1.0) -> np.ndarray:
+        """One V-cycle for (c*M + dt*a*K) x = t with zero initial guess on `level`."""
+        Bs, Dinvs, mus, chol = self.block(a, c)
         if level == len(self.sizes) - 1:
             return sla.cho_solve(chol, t)
         B, Dinv, mu = Bs[level], Dinvs[level], mus[level]
@@ -200,7 +201,7 @@ class Hierarchy:
         x = chebyshev_smooth(B, Dinv, t, np.zeros_like(t), lo, hi, self.deg)
         r = t - B @ x
         P = self.P[level]
-        e = self.vcycle(a, P.T @ r, level + 1)
+        e = self.vcycle(a, P.T @ r, level + 1, c)
         x = x + P @ e
         x = chebyshev_smooth(B, Dinv, t, x, lo, hi, self.deg)
         return x
@@ -226,12 +227,17 @@ def ldu(A):
 
 
 def preconditioner_matrix(kind, A):
-    """Atil of the stage preconditioner: D, L + D, or L1 D (Section 3.1)."""
+    """Atil of the stage preconditioner (Section 3.1): D (P_D), L + D (P_L), U + D (P_U), or L1 D (P_LD).
+
+    The same Atil serves both splittings: I (x) M + dt Atil (x) K for the AI form and
+    Atil^{-1} (x) M + dt I (x) K for the IA form."""
     A = np.asarray(A, dtype=np.float64)
     if kind == "jacobi":
         return np.diag(np.diag(A))
     if kind == "gs_lower":
         return np.tril(A)
+    if kind == "gs_upper":
+        return np.triu(A)
     if kind == "rana_ld":
         L1, D, _ = ldu(A)
         return L1 @ np.diag(D)
@@ -241,22 +247,28 @@ def preconditioner_matrix(kind, A):
 def apply_block_preconditioner(kind, A, dt, K, v, block_solve):
     """Apply P^{-1} for the AI-form stage preconditioner P = I (x) M + dt Atil (x) K.
 
-    kind: "jacobi" (P_D), "gs_lower" (P_L) or "rana_ld" (P_LD); v is stage-major (s*n,).
+    kind: "jacobi" (P_D), "gs_lower" (P_L), "gs_upper" (P_U) or "rana_ld" (P_LD); v is
+    stage-major (s*n,). Atil is triangular, so P is block triangular and is inverted by
+    block substitution: forward (i = 0, 1, ...) for a lower Atil, backward for an upper one,
+        z_i = B_i^{-1} (v_i - dt K sum_{j already solved} atil_ij z_j).
     block_solve(i, t) must return (an approximation of) B_i^{-1} t with
     B_i = M + dt*atil_ii*K.
     """
     Atil = preconditioner_matrix(kind, A)
     s = Atil.shape[0]
+    order = range(s - 1, -1, -1) if kind == "gs_upper" else range(s)
     V = np.asarray(v).reshape(s, -1)
     Z = np.zeros_like(V)
-    for i in range(s):
+    done = []
+    for i in order:
         t = V[i].copy()
-        if i > 0 and kind != "jacobi":
+        if done and kind != "jacobi":
             w = np.zeros_like(t)
-            for j in range(i):
+            for j in done:
                 w += Atil[i, j] * Z[j]
             t = t - dt * (K @ w)
         Z[i] = block_solve(i, t)
+        done.append(i)
     return Z.ravel()
 
 
@@ -276,3 +288,47 @@ def vcycle_block_solver(hier: Hierarchy, A):
     """block_solve applying one V-cycle of `hier` to every diagonal block; A is Atil or its diagonal."""
     d = _diagonal(A)
     return lambda i, t: hier.vcycle(d[i], t)
+
+
+# ---------------------------------------------------------------- IA form (eq:block_struct_IA)
+
+
+def apply_ia_block_preconditioner(kind, A, dt, M, K, v, block_solve):
+    """Apply P^{-1} for the IA-form stage preconditioner P = Atil^{-1} (x) M + dt I (x) K
+    (eq:pcbjac, eq:pcbgs, eq:pcranald as printed, for eq:block_struct_IA).
+
+    Atil is triangular, so C = Atil^{-1} is triangular too and P is block triangular with diagonal
+    blocks c_ii M + dt K (c_ii = 1/atil_ii); the stages are coupled through M:
+        z_i = B_i^{-1} (v_i - M sum_{j already solved} c_ij z_j).
+    block_solve(i, t) must return (an approximation of) (c_ii M + dt K)^{-1} t.
+    """
+    Atil = preconditioner_matrix(kind, A)
+    C = np.linalg.inv(Atil)
+    s = Atil.shape[0]
+    order = range(s - 1, -1, -1) if kind == "gs_upper" else range(s)
+    V = np.asarray(v).reshape(s, -1)
+    Z = np.zeros_like(V)
+    done = []
+    for i in order:
+        t = V[i].copy()
+        if done and kind != "jacobi":
+            w = np.zeros_like(t)
+            for j in done:
+                w += C[i, j] * Z[j]
+            t = t - M @ w
+        Z[i] = block_solve(i, t)
+        done.append(i)
+    return Z.ravel()
+
+
+def exact_ia_block_solver(M, K, Atil, dt):
+    """block_solve inverting every IA diagonal block (1/atil_ii) M + dt K exactly (sparse LU)."""
+    d = _diagonal(Atil)
+    lus = [spla.splu(((1.0 / d[i]) * M + dt * K).tocsc()) for i in range(d.size)]
+    return lambda i, t: lus[i].solve(t)
+
+
+def vcycle_ia_block_solver(hier: Hierarchy, Atil):
+    """block_solve applying one V-cycle of `hier` to every IA diagonal block (1/atil_ii) M + dt K."""
+    d = _diagonal(Atil)
+    return lambda i, t: hier.vcycle(1.0, t, c=1.0 / d[i])

@@ -41,6 +41,21 @@ def coupled_matrix(M, K, A, dt):
     return (sp.kron(sp.identity(s), M) + dt * sp.kron(sp.csr_matrix(np.asarray(A)), K)).tocsc()
 
 
+def coupled_matrix_ia(M, K, A, dt):
+    """Butcher's IA form A^{-1} (x) M + dt I_s (x) K (eq:block_struct_IA) acting on the stage combinations
+    w = (A (x) I) k (eq:butcherw, eq:stageeqw); the right-hand side is the same f as in the AI form."""
+    A = np.asarray(A, dtype=np.float64)
+    s = A.shape[0]
+    return (sp.kron(sp.csr_matrix(np.linalg.inv(A)), M) + dt * sp.kron(sp.identity(s), K)).tocsc()
+
+
+def stages_from_w(A, w):
+    """k = (A^{-1} (x) I) w: undo eq:butcherw (one small solve with A for all nodes at once)."""
+    A = np.asarray(A, dtype=np.float64)
+    s = A.shape[0]
+    return np.linalg.solve(A, np.asarray(w).reshape(s, -1)).ravel()
+
+
 def stage_rhs(K, u, s, F=None):
     """Right-hand side f_i = -K u^n + F_i, identical for every stage when F is constant in time."""
     f = -(K @ u)
@@ -154,16 +169,28 @@ def dense_solve(M, K, A, dt, rhs):
     return np.linalg.solve(Acal, rhs)
 
 
-def run(N, kappa, tab, dt, nsteps, u0, F=None, tier="coupled", return_stages=False):
-    """Integrate nsteps steps; returns the list [u^0, u^1, ..., u^nsteps] (and stages).
+def run(N, kappa, tab, dt, nsteps, u0, F=None, tier="coupled", return_stages=False, splitting="AI"):
+    """Integrate nsteps steps; returns the list [u^0, u^1, ..., u^nsteps] (and the stage unknowns).
 
-    tier: "coupled" (tier 2), "decoupled" (tier 3) or "dense" (tier 1).
+    tier: "coupled" (tier 2), "decoupled" (tier 3, AI only) or "dense" (tier 1).
+    splitting: "AI" solves eq:block_struct_AI for k; "IA" solves eq:block_struct_IA for w and
+    recovers k = (A^{-1} (x) I) w for the update (the stage unknowns returned are then w).
     """
     M, K = fem.assemble(N, kappa)
     A = np.asarray(tab["A"])
     b = np.asarray(tab["b"])
     s = b.size
-    if tier == "coupled":
+    if splitting not in ("AI", "IA"):
+        raise ValueError(splitting)
+    if splitting == "IA":
+        if tier == "coupled":
+            solver = spla.splu(coupled_matrix_ia(M, K, A, dt)).solve
+        elif tier == "dense":
+            Ad = coupled_matrix_ia(M, K, A, dt).toarray()
+            solver = lambda r: np.linalg.solve(Ad, r)  # noqa: E731
+        else:
+            raise ValueError(tier)
+    elif tier == "coupled":
         solver = CoupledLU(M, K, A, dt).solve
     elif tier == "decoupled":
         solver = DecoupledLU(M, K, A, dt).solve
@@ -176,8 +203,9 @@ def run(N, kappa, tab, dt, nsteps, u0, F=None, tier="coupled", return_stages=Fal
     ks = []
     u = us[0]
     for _ in range(nsteps):
-        k = solver(stage_rhs(K, u, s, F))
-        ks.append(k)
+        x = solver(stage_rhs(K, u, s, F))
+        ks.append(x)
+        k = stages_from_w(A, x) if splitting == "IA" else x
         u = update(u, k, b, dt)
         us.append(u)
     if return_stages:

@@ -140,7 +140,7 @@ def test_ldu_factorisation():
     assert D[0] == 2.0 and D[1] == 5.0 - 4.0 * 1.0 / 2.0 and L1[1, 0] == 2.0 and U1[0, 1] == 0.5
 
 
-@pytest.mark.parametrize("kind", ["jacobi", "gs_lower", "rana_ld"])
+@pytest.mark.parametrize("kind", ["jacobi", "gs_lower", "gs_upper", "rana_ld"])
 def test_exact_block_preconditioner_definition(kind):
     # with exact blocks, P^{-1} v solves I (x) M + dt Atil (x) K with Atil = D, L + D or L1 D
     N, dt = 10, 1e-2
@@ -148,7 +148,8 @@ def test_exact_block_preconditioner_definition(kind):
     M, K = fem.assemble(N, kap)
     A = T.radau_iia(3)["A"]
     L1, D, U1 = mg.ldu(A)
-    Atil = {"jacobi": np.diag(np.diag(A)), "gs_lower": np.tril(A), "rana_ld": L1 @ np.diag(D)}[kind]
+    Atil = {"jacobi": np.diag(np.diag(A)), "gs_lower": np.tril(A), "gs_upper": np.triu(A),
+            "rana_ld": L1 @ np.diag(D)}[kind]
     v = np.random.default_rng(5).standard_normal(3 * (N - 1) ** 2)
     z = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.exact_block_solver(M, K, Atil, dt))
     P = _block_prec_matrix(M, K, Atil, dt)
@@ -165,3 +166,60 @@ def test_gs_lower_is_exact_for_dirk():
     x = np.random.default_rng(6).standard_normal(3 * (N - 1) ** 2)
     z = mg.apply_block_preconditioner("gs_lower", A, dt, K, Acal @ x, mg.exact_block_solver(M, K, A, dt))
     assert np.linalg.norm(z - x) < 1e-12 * np.linalg.norm(x)
+    # and the block upper variant is exact for the transposed system (A^T upper triangular): backward substitution
+    AcalT = step.coupled_matrix(M, K, A.T, dt)
+    zt = mg.apply_block_preconditioner("gs_upper", A.T, dt, K, AcalT @ x, mg.exact_block_solver(M, K, A, dt))
+    assert np.linalg.norm(zt - x) < 1e-12 * np.linalg.norm(x)
+    # P_LD is exact for a DIRK too: A = L1 D with U1 = I
+    zr = mg.apply_block_preconditioner("rana_ld", A, dt, K, Acal @ x, mg.exact_block_solver(M, K, A, dt))
+    assert np.linalg.norm(zr - x) < 1e-12 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------- IA-form preconditioners
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "gs_lower", "gs_upper", "rana_ld"])
+def test_exact_ia_block_preconditioner_definition(kind):
+    # with exact blocks, P^{-1} v solves Atil^{-1} (x) M + dt I (x) K, and equals the AI-form
+    # preconditioner applied to (Atil (x) I) v since P_IA = (Atil^{-1} (x) I) P_AI
+    N, dt = 10, 1e-2
+    kap = synth.grf_kappa(N, 4)
+    M, K = fem.assemble(N, kap)
+    A = T.radau_iia(3)["A"]
+    L1, D, U1 = mg.ldu(A)
+    Atil = {"jacobi": np.diag(np.diag(A)), "gs_lower": np.tril(A), "gs_upper": np.triu(A),
+            "rana_ld": L1 @ np.diag(D)}[kind]
+    n = (N - 1) ** 2
+    v = np.random.default_rng(5).standard_normal(3 * n)
+    z = mg.apply_ia_block_preconditioner(kind, A, dt, M, K, v, mg.exact_ia_block_solver(M, K, Atil, dt))
+    P = step.coupled_matrix_ia(M, K, Atil, dt)
+    assert np.linalg.norm(P @ z - v) < 1e-12 * np.linalg.norm(v)
+    mixed = (Atil @ v.reshape(3, -1)).ravel()
+    z_ai = mg.apply_block_preconditioner(kind, A, dt, K, mixed, mg.exact_block_solver(M, K, Atil, dt))
+    assert np.linalg.norm(z - z_ai) < 1e-12 * np.linalg.norm(z)
+
+
+def test_ia_gs_lower_is_exact_for_dirk():
+    N, dt = 10, 1e-2
+    kap = synth.grf_kappa(N, 4)
+    M, K = fem.assemble(N, kap)
+    A = T.alexander()["A"]
+    x = np.random.default_rng(6).standard_normal(3 * (N - 1) ** 2)
+    v = step.coupled_matrix_ia(M, K, A, dt) @ x
+    z = mg.apply_ia_block_preconditioner("gs_lower", A, dt, M, K, v, mg.exact_ia_block_solver(M, K, A, dt))
+    assert np.linalg.norm(z - x) < 1e-12 * np.linalg.norm(x)
+
+
+def test_vcycle_is_homogeneous_in_the_block():
+    # one V-cycle on c M + dt a K: Jacobi-Chebyshev is invariant under scaling the operator and the coarse
+    # solve scales with it, so V(B/c') = c' V(B); the IA block (1/a) M + dt K is (1/a)(M + dt a K)
+    N, dt = 64, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    hier = mg.Hierarchy(N, kap, dt, coarse_n=8)
+    t = np.random.default_rng(10).standard_normal((N - 1) ** 2)
+    for a in (0.2, 0.42):
+        x1 = hier.vcycle(1.0, t, c=1.0 / a)
+        x2 = a * hier.vcycle(a, t)
+        assert np.linalg.norm(x1 - x2) < 1e-12 * np.linalg.norm(x2)
+        # and it is not the identity map of the unscaled block (the scale matters)
+        assert np.linalg.norm(hier.vcycle(a, t) - x1) > 0.1 * np.linalg.norm(x1)

@@ -130,3 +130,61 @@ def test_dirk_sequential_solve():
         r = -(K @ (u + dt * sum(A[i, j] * kk[j] for j in range(i))))
         kk.append(spla.spsolve((M + dt * A[i, i] * K).tocsc(), r))
     assert np.linalg.norm(k - np.concatenate(kk)) < 1e-12 * np.linalg.norm(k)
+
+
+# ---------------------------------------------------------------- IA splitting (eq:butcherw, eq:block_struct_IA)
+
+
+def test_ia_config1_decay_closed_form():
+    # the IA form is a change of unknowns only: config 1 still decays as R(-dt lam11)^n
+    N, dt = 32, 1.0 / 32
+    u0 = synth.sine_mode_vector(N, 1, 1)
+    us = step.run(N, None, T.radau_iia_printed(2), dt, 10, u0, splitting="IA")
+    R = _pade_radau2(-dt * _lam(N, 1, 1))
+    for n in range(11):
+        assert np.linalg.norm(us[n] - R**n * u0) <= 1e-12 * np.linalg.norm(R**n * u0)
+
+
+@pytest.mark.parametrize("tabname", ["radau3", "gl4", "lobatto", "alexander"])
+def test_ia_unknowns_are_stage_combinations(tabname):
+    # w_i = sum_j a_ij k_j (eq:butcherw) and both forms give the same step, for any invertible A
+    tab = {"radau3": T.radau_iia(3), "gl4": T.gauss_legendre(4), "lobatto": T.lobatto_iiic2(),
+           "alexander": T.alexander()}[tabname]
+    N, dt = 12, 2e-2
+    kap = synth.grf_kappa(N, 3)
+    u0 = synth.white_noise_u0(N, 4)
+    A = tab["A"]
+    s = A.shape[0]
+    ua, ka = step.run(N, kap, tab, dt, 3, u0, return_stages=True)
+    ui, wi = step.run(N, kap, tab, dt, 3, u0, return_stages=True, splitting="IA")
+    ud = step.run(N, kap, tab, dt, 3, u0, tier="dense", splitting="IA")
+    for n in range(1, 4):
+        assert np.linalg.norm(ui[n] - ua[n]) < 1e-13 * np.linalg.norm(ua[n])
+        assert np.linalg.norm(ud[n] - ua[n]) < 1e-13 * np.linalg.norm(ua[n])
+        k = ka[n - 1].reshape(s, -1)
+        w = np.stack([sum(A[i, j] * k[j] for j in range(s)) for i in range(s)])
+        assert np.linalg.norm(wi[n - 1] - w.ravel()) < 1e-12 * np.linalg.norm(w)
+
+
+def test_ia_stage_equations_written_out():
+    # eq:stageeqw for the heat equation: sum_j (A^{-1})_ij M w_j + K (u + dt w_i) = 0 stage by stage
+    N, dt = 10, 1e-2
+    kap = synth.grf_kappa(N, 5)
+    M, K = fem.assemble(N, kap)
+    tab = T.radau_iia(3)
+    u0 = synth.white_noise_u0(N, 6)
+    _, ws = step.run(N, kap, tab, dt, 1, u0, return_stages=True, splitting="IA")
+    W = ws[0].reshape(3, -1)
+    Ainv = np.linalg.inv(tab["A"])
+    for i in range(3):
+        r = sum(Ainv[i, j] * (M @ W[j]) for j in range(3)) + K @ (u0 + dt * W[i])
+        assert np.linalg.norm(r) < 1e-11 * np.linalg.norm(K @ u0)
+
+
+def test_ia_stiffly_accurate_update_is_last_w():
+    # Radau IIA: b^T A^{-1} = e_s^T, so u^{n+1} = u^n + dt w_s
+    N, dt = 16, 5e-3
+    kap = synth.grf_kappa(N, 3)
+    u0 = synth.white_noise_u0(N, 4)
+    us, ws = step.run(N, kap, T.radau_iia(3), dt, 1, u0, return_stages=True, splitting="IA")
+    assert np.linalg.norm(us[0] + dt * ws[0].reshape(3, -1)[2] - us[1]) < 1e-14 * np.linalg.norm(us[1])
