@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="time steps in the CPU oracle sample")
-    ap.add_argument("--precond", choices=["gs", "jacobi", "rana"], default="gs")
+    ap.add_argument("--precond", choices=["gs", "jacobi", "rana", "gsu"], default="gs")
+    ap.add_argument("--splitting", choices=["ai", "ia"], default="ai",
+                    help="stage formulation: eq:block_struct_AI (k) or eq:block_struct_IA (w = A k)")
     ap.add_argument("--orth", choices=["cgs2", "selective"], default="cgs2")
     ap.add_argument("--guess", choices=["zero", "prev"], default="zero")
     ap.add_argument("--restart", type=int, default=30)
@@ -61,9 +63,10 @@ def parse():
 
 
 def solver_options(P, args):
-    return dict(precond={"gs": P.PC_GS_LOWER, "jacobi": P.PC_JACOBI, "rana": P.PC_RANA_LD}[args.precond],
+    return dict(precond={"gs": P.PC_GS_LOWER, "jacobi": P.PC_JACOBI, "rana": P.PC_RANA_LD, "gsu": P.PC_GS_UPPER}[args.precond],
                 orth={"cgs2": P.ORTH_CGS2, "selective": P.ORTH_CGS_SELECTIVE}[args.orth],
                 initial_guess={"zero": P.GUESS_ZERO, "prev": P.GUESS_PREV}[args.guess],
+                splitting={"ai": P.SPLIT_AI, "ia": P.SPLIT_IA}[args.splitting],
                 restart=args.restart, mg_coarse_n=args.coarse_n, rtol=1e-10)
 
 
@@ -203,12 +206,14 @@ def main():
         "dtype": {"f32": "f64+f32", "bf16": "f64+bf16", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"diffusion Q1 {N}x{N}, kappa=exp(GRF seed 1), RadauIIA(3), dt=1e-3, "
-                               f"FGMRES({args.restart}) rtol 1e-10, P_{ {'gs': 'L', 'jacobi': 'D', 'rana': 'LD'}[args.precond]} + "
-                               f"1 GMG V-cycle Cheb(2), MG {args.precision}",
+                               f"FGMRES({args.restart}) rtol 1e-10, P_{ {'gs': 'L', 'jacobi': 'D', 'rana': 'LD', 'gsu': 'U'}[args.precond]} + "
+                               f"1 GMG V-cycle Cheb(2), MG {args.precision}"
+                               + (", IA splitting" if args.splitting == "ia" else ""),
                    "N": N, "dofs": n, "stages": s},
         "fgmres_its_per_step": stats["fgmres_its_total"] / max(1, args.steps),
         "setup_s": setup_s,
-        "solver": {"precond": args.precond, "orth": args.orth, "guess": args.guess, "restart": args.restart,
+        "solver": {"precond": args.precond, "splitting": args.splitting, "orth": args.orth, "guess": args.guess,
+                   "restart": args.restart,
                    "coarse_n": args.coarse_n},
         "error_vs_oracle": golden_error(uh, args.steps),
     }

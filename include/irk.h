@@ -16,11 +16,13 @@
  * and invertible A make every stage vanish on the boundary.
  *
  * The system is solved by right-preconditioned FGMRES. The preconditioner is the
- * block Jacobi (eq:pcbjac), block lower Gauss-Seidel (eq:pcbgs) or Rana-LD
- * (eq:pcranald) stage preconditioner, in the AI form  I (x) M + dt * Atil (x) K  with
- * Atil = D or L + D of A = L + D + U, or Atil = L1 D of A = L1 D U1 (unit triangular
- * L1, U1); each diagonal block M + dt*atil_ii*K is approximated by one geometric
- * multigrid V-cycle (Section 3.1).
+ * block Jacobi (eq:pcbjac), block lower Gauss-Seidel (eq:pcbgs), its block upper
+ * variant, or Rana-LD (eq:pcranald) stage preconditioner, in the AI form
+ * I (x) M + dt * Atil (x) K  with Atil = D, L + D or U + D of A = L + D + U, or
+ * Atil = L1 D of A = L1 D U1 (unit triangular L1, U1); each diagonal block
+ * M + dt*atil_ii*K is approximated by one geometric multigrid V-cycle (Section 3.1).
+ * A triangular Atil is inverted by block forward (lower) or backward (upper)
+ * substitution.
  *
  * Conventions for every entry point:
  *  - Return value: IRK_OK (0) or a negative irk_status. After an error,
@@ -57,10 +59,15 @@ typedef enum {
   IRK_EBREAKDOWN = -5   /* non-finite value met inside the Krylov iteration    */
 } irk_status;
 
-enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2 };  /* eq:pcbjac, eq:pcbgs, eq:pcranald */
+/* eq:pcbjac, eq:pcbgs, eq:pcranald, and the block upper-triangular variant of eq:pcbgs (Section 3.1) */
+enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2, IRK_PC_GS_UPPER = 3 };
 enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precision */
 enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1 };    /* Gram-Schmidt variant */
 enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial guess */
+/* Stage formulation (Section 2.4): AI solves eq:block_struct_AI for the stage derivatives k;
+ * IA solves eq:block_struct_IA, (A^{-1} (x) M + dt I (x) K) w = f, for w = (A (x) I) k
+ * (eq:butcherw, eq:stageeqw); A must then be invertible. */
+enum { IRK_SPLIT_AI = 0, IRK_SPLIT_IA = 1 };
 
 /* Butcher tableau (Section 2): A is s x s row-major, b and c have s entries.
  * Host memory; copied at stepper creation. */
@@ -73,7 +80,7 @@ typedef struct {
 
 /* Solver options; fill with irk_options_default() and override fields. */
 typedef struct {
-  int precond;        /* IRK_PC_JACOBI, IRK_PC_GS_LOWER or IRK_PC_RANA_LD          */
+  int precond;        /* IRK_PC_JACOBI, IRK_PC_GS_LOWER, IRK_PC_RANA_LD, IRK_PC_GS_UPPER */
   double rtol;        /* stop when |f - Acal k|_2 <= rtol * |f|_2 (true residual)  */
   int restart;        /* FGMRES restart length m, 1..32                           */
   int max_it;         /* total FGMRES iterations allowed per stage solve          */
@@ -87,6 +94,7 @@ typedef struct {
   int initial_guess;  /* IRK_GUESS_ZERO or IRK_GUESS_PREV (previous step's k)     */
   int use_graphs;     /* 1: replay each Krylov iteration as a captured HIP graph;  
                          0: launch every kernel eagerly (same arithmetic)          */
+  int splitting;      /* IRK_SPLIT_AI (default) or IRK_SPLIT_IA                    */
 } irk_options;
 
 /* Per-call statistics (host struct, filled if non-NULL). */
@@ -130,8 +138,8 @@ int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *
  * multigrid hierarchy (level diffusivities, power-iteration estimates of mu per
  * level and diagonal block, the coarsest-level inverse) and the Krylov
  * workspace. Every eigenvalue of A must have positive real part and every
- * a_ii > 0 (Rana-LD: every LDU pivot > 0) (IRK_EINVAL otherwise). The problem must
- * outlive the stepper. */
+ * a_ii > 0 (Rana-LD: every LDU pivot > 0), and A must be invertible for IRK_SPLIT_IA
+ * (IRK_EINVAL otherwise). The problem must outlive the stepper. */
 int irk_stepper_create(irk_stepper **out, const irk_problem *p, const irk_tableau *tab,
                        double dt, const irk_options *opts, void *stream);
 void irk_stepper_destroy(irk_stepper *st);
@@ -140,13 +148,18 @@ void irk_stepper_destroy(irk_stepper *st);
  * n or NULL (F = 0); f: device s*n. */
 int irk_stage_rhs(const irk_stepper *st, const double *u, const double *F, double *f, void *stream);
 
-/* a2 (eq:block_struct_AI): y = (I (x) M + dt * A (x) K) x, or with A^T when transpose != 0.
+/* a2 (eq:block_struct_AI): y = (I (x) M + dt * A (x) K) x, or with A^T when transpose != 0;
+ * with IRK_SPLIT_IA (eq:block_struct_IA): y = (A^{-1} (x) M + dt I (x) K) x, or with A^{-T}.
  * x, y: device s*n, no overlap. */
 int irk_apply_stage_operator(const irk_stepper *st, const double *x, double *y, int transpose, void *stream);
 
-/* a3 (eq:pcbjac / eq:pcbgs / eq:pcranald, AI form): z = P^{-1} v with the stepper's block
- * preconditioner, every diagonal block solve replaced by one V-cycle. With transpose != 0 the
- * preconditioner of the transposed system (built from A^T) is applied. v, z: device s*n. */
+/* a3 (eq:pcbjac / eq:pcbgs / eq:pcranald): z = P^{-1} v with the stepper's block
+ * preconditioner, every diagonal block solve replaced by one V-cycle. AI splitting:
+ * P = I (x) M + dt Atil (x) K, stages coupled through K. IA splitting (the printed form):
+ * P = Atil^{-1} (x) M + dt I (x) K, stages coupled through M, diagonal blocks
+ * (1/atil_ii) M + dt K, whose V-cycle is atil_ii times the V-cycle of M + dt atil_ii K.
+ * With transpose != 0 the preconditioner of the transposed system (built from A^T) is
+ * applied. v, z: device s*n. */
 int irk_apply_preconditioner(const irk_stepper *st, const double *v, double *z, int transpose, void *stream);
 
 /* a4 (Section 3.1 diagonal blocks): z = one V-cycle for (M + dt*atil_ii*K) z = t with zero
@@ -155,12 +168,14 @@ int irk_apply_preconditioner(const irk_stepper *st, const double *v, double *z, 
 int irk_vcycle(const irk_stepper *st, int stage, const double *t, double *z, void *stream);
 
 /* a5: solve (I (x) M + dt*A (x) K) k = f (A^T when transpose != 0) by FGMRES to the
- * stepper's rtol from a zero initial guess. f, k: device s*n. Synchronises. */
+ * stepper's rtol from a zero initial guess; with IRK_SPLIT_IA the unknown is w and the
+ * operator that of irk_apply_stage_operator. f, k: device s*n. Synchronises. */
 int irk_solve_stages(irk_stepper *st, const double *f, double *k, int transpose, irk_stats *stats, void *stream);
 
 /* a1+a5+a6: advance u (device n, in/out) by nsteps time steps of size dt with forcing F
- * (device n or NULL), u^{n+1} = u^n + dt * sum_i b_i k_i. On IRK_ENOCONV u holds the last
- * step that converged and stats->failed_step names the failing step. Synchronises. */
+ * (device n or NULL), u^{n+1} = u^n + dt * sum_i b_i k_i (IA: dt * sum_i (A^{-T} b)_i w_i).
+ * On IRK_ENOCONV u holds the last step that converged and stats->failed_step names the
+ * failing step. Synchronises. */
 int irk_advance(irk_stepper *st, double *u, const double *F, int nsteps, irk_stats *stats, void *stream);
 
 /* a8+a9: discrete adjoint of nsteps steps from u0 (device n) with F = 0. Given

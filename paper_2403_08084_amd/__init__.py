@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libirk.so")
 
 IRK_OK, IRK_EINVAL, IRK_ENOMEM, IRK_EHIP, IRK_ENOCONV, IRK_EBREAKDOWN = 0, -1, -2, -3, -4, -5
-PC_JACOBI, PC_GS_LOWER, PC_RANA_LD = 0, 1, 2
+PC_JACOBI, PC_GS_LOWER, PC_RANA_LD, PC_GS_UPPER = 0, 1, 2, 3
+SPLIT_AI, SPLIT_IA = 0, 1
 F64, F32, BF16 = 0, 1, 2
 ORTH_CGS2, ORTH_CGS_SELECTIVE = 0, 1
 GUESS_ZERO, GUESS_PREV = 0, 1
@@ -53,6 +54,7 @@ class Options(ctypes.Structure):
         ("orth", ctypes.c_int),
         ("initial_guess", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("splitting", ctypes.c_int),
     ]
 
 

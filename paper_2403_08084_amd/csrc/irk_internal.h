@@ -71,16 +71,18 @@ void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, 
 
 // ---------------------------------------------------------------- stencils (k_stencil.hip)
 // y = (I (x) M + dt*A (x) K) x  (coefficients `a`, row-major s x s); if f != nullptr: y = f - that.
+// ia: y = (A (x) M + dt*I (x) K) x instead (the IA form passes A^{-1} as `a`).
 void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
-                           const Coefs& a, double dt, hipStream_t st);
+                           const Coefs& a, double dt, hipStream_t st, bool ia = false);
 // f_i = -K u + F (F may be null), i = 0..s-1
 void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st);
 // y = M x or y = K x
 void launch_mass(const double* x, double* y, Geom g, hipStream_t st);
 void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st);
-// t = vscale * v - dt * K * sum_{j<i} coef[j] z_j  (z_j planes at z + j*plane; vscale: device scalar or null = 1)
-void launch_gs_couple(const double* v, const double* vscale, const double* z, int i, const Coefs& row, double dt,
-                      const double* kappa, double* t, Geom g, hipStream_t st);
+// t = vmul * vscale * v - dt * Op * sum_{q<nz} row[q] z_q  (z_q planes at z + q*plane; vscale: device scalar or
+// null = 1; Op = K, or M if mass)
+void launch_gs_couple(const double* v, const double* vscale, const double* z, int nz, const Coefs& row, double dt,
+                      const double* kappa, double* t, Geom g, hipStream_t st, int mass = 0, double vmul = 1.0);
 // u += dt * sum_i b_i k_i
 void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st);
 // f_i = dt * b_i * lam
@@ -100,11 +102,14 @@ void launch_scale(double* x, long n, const double* inv_norm2_src, hipStream_t st
 // Block Gauss-Seidel coupling folded into the finest-level kernels: their right-hand side becomes
 // t = tscale * v - dt * K * sum_{q<nz} a[q] z_q  (z_q = z + q*zstride, FP64 padded planes).
 struct Couple {
-  const double* z;
-  long zstride;
-  int nz;  // 0: no coupling
-  double dt;
-  double a[kMaxStages];
+  const double* z = nullptr;  // first coupled stage plane
+  long zstride = 0;
+  int nz = 0;                 // number of coupled stages; 0: no coupling
+  int mass = 0;               // coupling operator: 0 = stiffness K (element kappa), 1 = mass M
+  double dt = 0;              // t -= dt * Op(sum_q a_q z_q)
+  double mh = 0;              // h^2/36 of the level (mass stencil)
+  double vmul = 1.0;          // the right-hand side t is scaled by vmul (and the device scalar)
+  double a[kMaxStages] = {};
 };
 // prec: 0 = FP64 storage/compute, 1 = FP32, 2 = BF16 storage / FP32 compute.
 // DOWN: pre-smooth from zero on the fine level, write x, restrict the residual into tc (coarse).

@@ -96,9 +96,10 @@ __device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ k
 }
 
 
-// Block Gauss-Seidel coupling inside the finest-level tiles: w = sum_q a_q z_q is loaded on the
+// Block-triangular stage coupling inside the finest-level tiles: w = sum_q a_q z_q is loaded on the
 // region plus one node (row length RX + 2) together with the other tile loads, staged in LDS,
-// and t -= dt * K w is applied on the region with the region's kappa tile.
+// and t -= dt * K w (AI form, with the region's kappa tile) or t -= M w (IA form) is applied on the
+// region.
 template <typename TC, int RX, int RY>
 struct CoupleLoad {
   static constexpr int WX = RX + 2, CNT = WX * (RY + 2), NL = (CNT + NT - 1) / NT;
@@ -136,12 +137,18 @@ __device__ __forceinline__ void couple_apply(TC* sT, const TC* sW, const TC* sK,
     const int p = (lj + 1) * WX + (li + 1);
     const int q = lj * KX + li;
     const TC kSW = sK[q], kSE = sK[q + 1], kNW = sK[q + KX], kNE = sK[q + KX + 1];
-    const TC Kw = (TC)(2.0 / 3.0) * (kSW + kSE + kNW + kNE) * sW[p] -
-                  (TC)(1.0 / 6.0) * ((kNE + kSE) * sW[p + 1] + (kNW + kSW) * sW[p - 1] + (kNE + kNW) * sW[p + WX] +
-                                     (kSE + kSW) * sW[p - WX]) -
-                  (TC)(1.0 / 3.0) * (kNE * sW[p + WX + 1] + kNW * sW[p + WX - 1] + kSE * sW[p - WX + 1] +
-                                     kSW * sW[p - WX - 1]);
-    sT[idx] -= dt * Kw;
+    TC opw;
+    if (cp.mass) {
+      opw = (TC)cp.mh * ((TC)16 * sW[p] + (TC)4 * (sW[p + 1] + sW[p - 1] + sW[p + WX] + sW[p - WX]) +
+                         (sW[p + WX + 1] + sW[p + WX - 1] + sW[p - WX + 1] + sW[p - WX - 1]));
+    } else {
+      opw = (TC)(2.0 / 3.0) * (kSW + kSE + kNW + kNE) * sW[p] -
+            (TC)(1.0 / 6.0) * ((kNE + kSE) * sW[p + 1] + (kNW + kSW) * sW[p - 1] + (kNE + kNW) * sW[p + WX] +
+                               (kSE + kSW) * sW[p - WX]) -
+            (TC)(1.0 / 3.0) * (kNE * sW[p + WX + 1] + kNW * sW[p + WX - 1] + kSE * sW[p - WX + 1] +
+                               kSW * sW[p - WX - 1]);
+    }
+    sT[idx] -= dt * opw;
   }
 }
 
@@ -159,7 +166,7 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
   const int N = g.N;
   const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
   const int ox = i0 - H, oy = j0 - H;
-  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = tscale ? (TC)(*tscale) : (TC)1;
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)((tscale ? *tscale : 1.0) * cp.vmul);
 
   {
     constexpr int CNT = RX * RY, NL = (CNT + NT - 1) / NT;
@@ -281,7 +288,7 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
   const int N = g.N;
   const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
   const int ox = i0 - H, oy = j0 - H;
-  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = tscale ? (TC)(*tscale) : (TC)1;
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)((tscale ? *tscale : 1.0) * cp.vmul);
 
   {
     constexpr int CNT = RX * RY, NL = (CNT + NT - 1) / NT;

@@ -143,7 +143,7 @@ __global__ void coarsen_kappa_kernel(const double* __restrict__ f, double* __res
 
 // ------------------------------------------------------------------ stencils
 
-template <int S>
+template <int S, bool IA>
 __global__ __launch_bounds__(BX* BY) void stage_operator_kernel(const double* __restrict__ x, double* __restrict__ y,
                                                                 const double* __restrict__ f,
                                                                 const double* __restrict__ kap, Geom g, Coefs a,
@@ -163,10 +163,17 @@ __global__ __launch_bounds__(BX* BY) void stage_operator_kernel(const double* __
   }
 #pragma unroll
   for (int r = 0; r < S; ++r) {
-    double acc = 0.0;
+    double acc = 0.0, val;
+    if (IA) {
+      // (A^{-1} (x) M + dt I (x) K) x: stage mixing on the mass term
 #pragma unroll
-    for (int q = 0; q < S; ++q) acc += a.a[r * kMaxStages + q] * Kx[q];
-    const double val = Mx[r] + dt * acc;
+      for (int q = 0; q < S; ++q) acc += a.a[r * kMaxStages + q] * Mx[q];
+      val = acc + dt * Kx[r];
+    } else {
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc += a.a[r * kMaxStages + q] * Kx[q];
+      val = Mx[r] + dt * acc;
+    }
     if (f)
       y[r * g.plane + p] = f[r * g.plane + p] - val;
     else
@@ -204,15 +211,19 @@ __global__ __launch_bounds__(BX* BY) void stiff_kernel(const double* __restrict_
 __global__ __launch_bounds__(BX* BY) void gs_couple_kernel(const double* __restrict__ v, const double* __restrict__ vscale,
                                                            const double* __restrict__ z, int ns, Coefs row, double dt,
                                                            const double* __restrict__ kap, double* __restrict__ t,
-                                                           Geom g) {
+                                                           Geom g, int use_mass, double vmul) {
   int i, j;
   if (!node_of_thread(g, i, j)) return;
   const int P = g.pitch;
   const long p = (long)j * P + i;
   const Kap k = load_kap(kap, p, P);
+  const double m = g.h * g.h / 36.0;
   double acc = 0.0;
-  for (int q = 0; q < ns; ++q) acc += row.a[q] * stiff(load_nb(z + q * g.plane, p, P), k);
-  t[p] = (vscale ? *vscale : 1.0) * v[p] - dt * acc;
+  for (int q = 0; q < ns; ++q) {
+    const Nb nb = load_nb(z + q * g.plane, p, P);
+    acc += row.a[q] * (use_mass ? mass(nb, m) : stiff(nb, k));
+  }
+  t[p] = vmul * (vscale ? *vscale : 1.0) * v[p] - dt * acc;
 }
 
 __global__ void update_kernel(double* __restrict__ u, const double* __restrict__ k, int s, Coefs b, double dt,
@@ -349,19 +360,28 @@ void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, 
   coarsen_kappa_kernel<<<flat_blocks((long)gc.N * gc.pitch), 256, 0, st>>>(fine, coarse, gf, gc);
 }
 
-void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
-                           const Coefs& a, double dt, hipStream_t st) {
+template <bool IA>
+void stage_operator_t(const double* x, double* y, const double* f, const double* kappa, Geom g, int s, const Coefs& a,
+                      double dt, hipStream_t st) {
   const dim3 grid = stencil_grid(g), blk(BX, BY);
   switch (s) {
-    case 1: stage_operator_kernel<1><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 2: stage_operator_kernel<2><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 3: stage_operator_kernel<3><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 4: stage_operator_kernel<4><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 5: stage_operator_kernel<5><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 6: stage_operator_kernel<6><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 7: stage_operator_kernel<7><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    default: stage_operator_kernel<8><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 1: stage_operator_kernel<1, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 2: stage_operator_kernel<2, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 3: stage_operator_kernel<3, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 4: stage_operator_kernel<4, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 5: stage_operator_kernel<5, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 6: stage_operator_kernel<6, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 7: stage_operator_kernel<7, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    default: stage_operator_kernel<8, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
   }
+}
+
+void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
+                           const Coefs& a, double dt, hipStream_t st, bool ia) {
+  if (ia)
+    stage_operator_t<true>(x, y, f, kappa, g, s, a, dt, st);
+  else
+    stage_operator_t<false>(x, y, f, kappa, g, s, a, dt, st);
 }
 void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st) {
   stage_rhs_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(u, F, f, kappa, g, s);
@@ -372,9 +392,9 @@ void launch_mass(const double* x, double* y, Geom g, hipStream_t st) {
 void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st) {
   stiff_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, y, kappa, g);
 }
-void launch_gs_couple(const double* v, const double* vscale, const double* z, int i, const Coefs& row, double dt,
-                      const double* kappa, double* t, Geom g, hipStream_t st) {
-  gs_couple_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(v, vscale, z, i, row, dt, kappa, t, g);
+void launch_gs_couple(const double* v, const double* vscale, const double* z, int nz, const Coefs& row, double dt,
+                      const double* kappa, double* t, Geom g, hipStream_t st, int mass, double vmul) {
+  gs_couple_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(v, vscale, z, nz, row, dt, kappa, t, g, mass, vmul);
 }
 void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st) {
   update_kernel<<<flat_blocks(g.plane), 256, 0, st>>>(u, k, s, b, dt, g.plane);

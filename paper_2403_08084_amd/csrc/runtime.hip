@@ -95,6 +95,11 @@ struct irk_stepper {
   // systems, and its diagonal (the diagonal blocks M + dt*pd_i*K)
   double Pt[2][kMaxStages * kMaxStages] = {};
   double pd[kMaxStages] = {};
+  // stage formulation: AI (unknowns k) or IA (unknowns w = (A (x) I) k)
+  bool ia = false;
+  double Op[2][kMaxStages * kMaxStages] = {};  // operator mixing: AI A / A^T (on K), IA A^{-1} / A^{-T} (on M)
+  double Ci[2][kMaxStages * kMaxStages] = {};  // IA preconditioner coupling Atil^{-1} (forward / transposed)
+  double bw[kMaxStages] = {};                  // update weights on the unknowns: AI b, IA A^{-T} b
   irk_options opt{};
   int prec = 0;
   Geom g{};
@@ -136,10 +141,19 @@ double* sigma_dev(irk_stepper* st) { return st->dres + 4L * RSTRIDE; }
 double* ycoef_dev(irk_stepper* st) { return st->dres + 5L * RSTRIDE; }
 constexpr long DRES_LEN = 6L * RSTRIDE;
 
+// stage-operator mixing coefficients for the forward or transposed system
 Coefs coefs_of(const irk_stepper* st, bool trans) {
   Coefs a{};
   for (int i = 0; i < st->s; ++i)
-    for (int j = 0; j < st->s; ++j) a.a[i * kMaxStages + j] = trans ? st->A[j * st->s + i] : st->A[i * st->s + j];
+    for (int j = 0; j < st->s; ++j) a.a[i * kMaxStages + j] = st->Op[trans ? 1 : 0][i * st->s + j];
+  return a;
+}
+
+// stage values U_i = u + dt sum_j mix_ij x_j in terms of the unknowns x: AI mix = A, IA mix = I
+Coefs mix_of(const irk_stepper* st) {
+  Coefs a{};
+  for (int i = 0; i < st->s; ++i)
+    for (int j = 0; j < st->s; ++j) a.a[i * kMaxStages + j] = st->ia ? (i == j ? 1.0 : 0.0) : st->A[i * st->s + j];
   return a;
 }
 
@@ -152,8 +166,40 @@ Coefs ptil_of(const irk_stepper* st, bool trans) {
 
 Coefs b_of(const irk_stepper* st) {
   Coefs b{};
-  for (int i = 0; i < st->s; ++i) b.a[i] = st->b[i];
+  for (int i = 0; i < st->s; ++i) b.a[i] = st->bw[i];
   return b;
+}
+
+// inverse of a small dense row-major s x s matrix by Gauss-Jordan elimination with partial
+// pivoting; false if a pivot is negligible against the matrix norm
+bool small_inverse(const double* A, int s, double* inv) {
+  double W[kMaxStages * 2 * kMaxStages];
+  double nrm = 0;
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      W[i * 2 * s + j] = A[i * s + j];
+      W[i * 2 * s + s + j] = (i == j) ? 1.0 : 0.0;
+      nrm = std::max(nrm, std::fabs(A[i * s + j]));
+    }
+  for (int k = 0; k < s; ++k) {
+    int pr = k;
+    for (int i = k + 1; i < s; ++i)
+      if (std::fabs(W[i * 2 * s + k]) > std::fabs(W[pr * 2 * s + k])) pr = i;
+    if (!(std::fabs(W[pr * 2 * s + k]) > 1e-13 * nrm)) return false;
+    if (pr != k)
+      for (int j = 0; j < 2 * s; ++j) std::swap(W[k * 2 * s + j], W[pr * 2 * s + j]);
+    const double d = W[k * 2 * s + k];
+    for (int j = 0; j < 2 * s; ++j) W[k * 2 * s + j] /= d;
+    for (int i = 0; i < s; ++i) {
+      if (i == k) continue;
+      const double f = W[i * 2 * s + k];
+      if (f != 0.0)
+        for (int j = 0; j < 2 * s; ++j) W[i * 2 * s + j] -= f * W[k * 2 * s + j];
+    }
+  }
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) inv[i * s + j] = W[i * 2 * s + s + j];
+  return true;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -445,28 +491,47 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
   return check_launch();
 }
 
-// z = P^{-1} (vscale * v), block Jacobi or block lower Gauss-Seidel in the AI form (vscale: device scalar or null)
+// z = P^{-1} (vscale * v) for the block-triangular stage preconditioner (vscale: device scalar or null).
+// AI form: P = I (x) M + dt Atil (x) K, z_i = B_i^{-1} (v_i - dt K sum_j atil_ij z_j).
+// IA form: P = Atil^{-1} (x) M + dt I (x) K, z_i = atil_ii B_i^{-1} (v_i - M sum_j c_ij z_j) with
+// C = Atil^{-1}, B_i = M + dt atil_ii K (one V-cycle is linear, so atil_ii scales its input).
 int precondition(irk_stepper* st, const double* v, const double* vscale, double* z, bool trans, hipStream_t s) {
   const long plane = st->g.plane;
+  const int ns = st->s;
   const Coefs a = ptil_of(st, trans);
-  for (int i = 0; i < st->s; ++i) {
+  const double* Ci = st->Ci[trans ? 1 : 0];
+  // Atil is lower triangular (forward substitution) except for P_U (backward substitution); stage i is
+  // coupled to the nc stages solved before it, which sit contiguously from stage j0 on
+  const bool upper = st->opt.precond == IRK_PC_GS_UPPER;
+  for (int step = 0; step < ns; ++step) {
+    const int i = upper ? ns - 1 - step : step;
+    const int j0 = upper ? i + 1 : 0;
+    const int nc = (st->opt.precond == IRK_PC_JACOBI) ? 0 : step;
+    const double vmul = st->ia ? st->pd[i] : 1.0;
     const double* vi = v + i * plane;
     double* zi = z + i * plane;
-    if (st->opt.precond != IRK_PC_JACOBI && i > 0) {
+    double row[kMaxStages] = {};
+    for (int q = 0; q < nc; ++q)
+      row[q] = st->ia ? vmul * Ci[i * ns + j0 + q] : a.a[i * kMaxStages + j0 + q];
+    if (nc > 0 || vmul != 1.0) {
       if (st->lv.size() > 1) {
-        // the coupling -dt K sum_{j<i} a_ij z_j is formed inside the finest-level kernels
+        // the coupling and the scale are applied inside the finest-level kernels
         Couple cp{};
-        cp.z = z;
+        cp.z = z + j0 * plane;
         cp.zstride = plane;
-        cp.nz = i;
-        cp.dt = st->dt;
-        for (int j = 0; j < i; ++j) cp.a[j] = a.a[i * kMaxStages + j];
+        cp.nz = nc;
+        cp.mass = st->ia ? 1 : 0;
+        cp.dt = st->ia ? 1.0 : st->dt;
+        cp.mh = st->g.h * st->g.h / 36.0;
+        cp.vmul = vmul;
+        for (int q = 0; q < nc; ++q) cp.a[q] = row[q];
         CHK(vcycle(st, i, vi, vscale, zi, s, &cp));
       } else {
-        Coefs row{};
-        for (int j = 0; j < i; ++j) row.a[j] = a.a[i * kMaxStages + j];
+        Coefs r{};
+        for (int q = 0; q < nc; ++q) r.a[q] = row[q];
         double* t = st->tmp2;
-        launch_gs_couple(vi, vscale, z, i, row, st->dt, st->prob->kappa, t, st->g, s);
+        launch_gs_couple(vi, vscale, z + j0 * plane, nc, r, st->ia ? 1.0 : st->dt, st->prob->kappa, t, st->g, s,
+                         st->ia ? 1 : 0, vmul);
         CHK(vcycle(st, i, t, nullptr, zi, s));
       }
     } else {
@@ -477,7 +542,7 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
 }
 
 int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s) {
-  launch_stage_operator(x, y, f, st->prob->kappa, st->g, st->s, coefs_of(st, trans), st->dt, s);
+  launch_stage_operator(x, y, f, st->prob->kappa, st->g, st->s, coefs_of(st, trans), st->dt, s, st->ia);
   return check_launch();
 }
 
@@ -809,6 +874,7 @@ void irk_options_default(irk_options* o) {
   o->orth = IRK_ORTH_CGS2;
   o->initial_guess = IRK_GUESS_ZERO;
   o->use_graphs = 1;
+  o->splitting = IRK_SPLIT_AI;
 }
 
 int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stream) {
@@ -939,8 +1005,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   irk_options o;
   irk_options_default(&o);
   if (opts) o = *opts;
-  if (o.precond != IRK_PC_JACOBI && o.precond != IRK_PC_GS_LOWER && o.precond != IRK_PC_RANA_LD)
-    return fail(IRK_EINVAL, "unknown precond");
+  if (o.precond < IRK_PC_JACOBI || o.precond > IRK_PC_GS_UPPER) return fail(IRK_EINVAL, "unknown precond");
   if (o.restart < 1 || o.restart > 32) return fail(IRK_EINVAL, "restart must be in 1..32");
   if (o.max_it < 1) return fail(IRK_EINVAL, "max_it must be >= 1");
   if (!(o.rtol > 0) || !(o.rtol < 1)) return fail(IRK_EINVAL, "rtol must be in (0, 1)");
@@ -952,6 +1017,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   if (o.initial_guess != IRK_GUESS_ZERO && o.initial_guess != IRK_GUESS_PREV)
     return fail(IRK_EINVAL, "unknown initial_guess");
   if (o.mg_coarse_n < 1) return fail(IRK_EINVAL, "mg_coarse_n must be >= 1");
+  if (o.splitting != IRK_SPLIT_AI && o.splitting != IRK_SPLIT_IA) return fail(IRK_EINVAL, "unknown splitting");
   const int s = tab->s;
   for (int i = 0; i < s * s; ++i)
     if (!std::isfinite(tab->A[i])) return fail(IRK_EINVAL, "non-finite tableau entry");
@@ -972,8 +1038,9 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   st->dt = dt;
   st->opt = o;
   {
-    // Atil: D, L + D (additive split, eq:pcbjac / eq:pcbgs) or L1 D of A = L1 D U1 (eq:pcranald);
-    // the transposed system A^T uses D, tril(A^T), or U1^T D (A^T = U1^T D L1^T has the same D)
+    // Atil: D, L + D, U + D (additive split, eq:pcbjac / eq:pcbgs and its upper variant) or L1 D of
+    // A = L1 D U1 (eq:pcranald); the transposed system A^T uses D, tril(A^T), triu(A^T) or U1^T D
+    // (A^T = U1^T D L1^T has the same D)
     double L1[kMaxStages * kMaxStages] = {}, U1[kMaxStages * kMaxStages] = {}, D[kMaxStages] = {};
     if (o.precond == IRK_PC_RANA_LD) {
       double W[kMaxStages * kMaxStages];
@@ -1001,6 +1068,9 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
         } else if (o.precond == IRK_PC_GS_LOWER) {
           f = (j <= i) ? tab->A[i * s + j] : 0.0;
           t = (j <= i) ? tab->A[j * s + i] : 0.0;
+        } else if (o.precond == IRK_PC_GS_UPPER) {
+          f = (j >= i) ? tab->A[i * s + j] : 0.0;
+          t = (j >= i) ? tab->A[j * s + i] : 0.0;
         } else {
           f = (j <= i) ? L1[i * s + j] * D[j] : 0.0;
           t = (j <= i) ? U1[j * s + i] * D[j] : 0.0;
@@ -1009,6 +1079,32 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
         st->Pt[1][i * s + j] = t;
       }
     for (int i = 0; i < s; ++i) st->pd[i] = st->Pt[0][i * s + i];
+  }
+  st->ia = o.splitting == IRK_SPLIT_IA;
+  {
+    double Ainv[kMaxStages * kMaxStages];
+    if (st->ia && !small_inverse(tab->A, s, Ainv)) {
+      delete st;
+      return fail(IRK_EINVAL, "the IA splitting needs an invertible A");
+    }
+    for (int i = 0; i < s; ++i) {
+      for (int j = 0; j < s; ++j) {
+        st->Op[0][i * s + j] = st->ia ? Ainv[i * s + j] : tab->A[i * s + j];
+        st->Op[1][i * s + j] = st->ia ? Ainv[j * s + i] : tab->A[j * s + i];
+      }
+      double bw = tab->b[i];
+      if (st->ia) {
+        bw = 0.0;
+        for (int j = 0; j < s; ++j) bw += Ainv[j * s + i] * tab->b[j];
+      }
+      st->bw[i] = bw;
+    }
+    if (st->ia)
+      for (int t = 0; t < 2; ++t)
+        if (!small_inverse(st->Pt[t], s, st->Ci[t])) {
+          delete st;
+          return fail(IRK_EINVAL, "singular preconditioner matrix");
+        }
   }
   st->prec = o.mg_precision;
   st->g = p->g;
@@ -1227,7 +1323,7 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
   launch_pack(lambda_T, lam, g, 1, s);
   long adv = 0;
   std::vector<Action> sch = revolve_schedule(nsteps, slots, adv);
-  const Coefs at = coefs_of(st, false);
+  const Coefs at = mix_of(st);
   const Coefs bb = b_of(st);
   st->have_prev = false;
   int done = 0;

@@ -18,14 +18,17 @@ def _setup(N, nsteps, dt):
     return kap, u0, ustar
 
 
-@pytest.mark.parametrize("nsnap", [2, 3, 100])
-def test_adjoint_matches_oracle(nsnap):
+@pytest.mark.parametrize("nsnap,split,pc", [(2, P.SPLIT_AI, P.PC_GS_LOWER), (3, P.SPLIT_AI, P.PC_GS_LOWER),
+                                            (100, P.SPLIT_AI, P.PC_GS_LOWER), (3, P.SPLIT_AI, P.PC_RANA_LD),
+                                            (3, P.SPLIT_IA, P.PC_GS_LOWER), (3, P.SPLIT_IA, P.PC_RANA_LD)])
+def test_adjoint_matches_oracle(nsnap, split, pc):
+    # the gradient of the discrete step map does not depend on the stage formulation or the preconditioner
     N, nsteps, dt = 32, 6, 1e-3
     kap, u0, ustar = _setup(N, nsteps, dt)
     fwd = adjoint.forward(N, kap, OT.radau_iia(3), dt, nsteps, u0)
     _, lamN = adjoint.objective(fwd[2], fwd[0][-1], ustar)
     lam0_o, g_o = adjoint.gradient(N, kap, OT.radau_iia(3), dt, nsteps, u0, lamN, fwd=fwd)
-    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, rtol=1e-13)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, rtol=1e-13, splitting=split, precond=pc)
     lam0, g, st = stp.adjoint(dev(u0), nsteps, nsnap, dev(lamN))
     assert rel(host(lam0), lam0_o) < 1e-9
     assert rel(host(g), g_o) < 1e-9

@@ -57,7 +57,7 @@ def test_vcycle_contracts():
 
 
 @pytest.mark.parametrize("kind,pc", [("jacobi", P.PC_JACOBI), ("gs_lower", P.PC_GS_LOWER),
-                                     ("rana_ld", P.PC_RANA_LD)])
+                                     ("gs_upper", P.PC_GS_UPPER), ("rana_ld", P.PC_RANA_LD)])
 @pytest.mark.parametrize("transpose", [False, True])
 @pytest.mark.parametrize("tname,N", [("radau3", 96), ("gl4", 64), ("radau2", 33)])
 def test_block_preconditioner(kind, pc, transpose, tname, N):
@@ -80,4 +80,28 @@ def test_block_preconditioner(kind, pc, transpose, tname, N):
     v = synth.random_stage_block(N, s, 11).ravel()
     z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
     ref = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.vcycle_block_solver(hier, Atil))
+    assert rel(z, ref) < 1e-12
+
+
+@pytest.mark.parametrize("kind,pc", [("jacobi", P.PC_JACOBI), ("gs_lower", P.PC_GS_LOWER),
+                                     ("gs_upper", P.PC_GS_UPPER), ("rana_ld", P.PC_RANA_LD)])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("tname,N", [("radau3", 96), ("gl4", 64), ("radau2", 33)])
+def test_ia_block_preconditioner(kind, pc, transpose, tname, N):
+    # IA form as printed: Atil^{-1} (x) M + dt I (x) K, stages coupled through M, one V-cycle per diagonal
+    # block (1/atil_ii) M + dt K; the oracle builds that V-cycle on the scaled block itself
+    dt = 1e-3
+    kap = synth.grf_kappa(N, 3)
+    M, K = fem.assemble(N, kap)
+    otab = {"radau3": OT.radau_iia(3), "gl4": OT.gauss_legendre(4), "radau2": OT.radau_iia(2)}[tname]
+    ptab = {"radau3": P.tableaux.radau_iia(3), "gl4": P.tableaux.gauss_legendre(4),
+            "radau2": P.tableaux.radau_iia(2)}[tname]
+    s = otab["A"].shape[0]
+    A = otab["A"].T if transpose else otab["A"]
+    Atil = mg.preconditioner_matrix(kind, A)
+    hier = mg.Hierarchy(N, kap, dt)
+    _, stp = make(N, kap, ptab, dt, precond=pc, splitting=P.SPLIT_IA)
+    v = synth.random_stage_block(N, s, 13).ravel()
+    z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
+    ref = mg.apply_ia_block_preconditioner(kind, A, dt, M, K, v, mg.vcycle_ia_block_solver(hier, Atil))
     assert rel(z, ref) < 1e-12

@@ -2,6 +2,7 @@
 against the oracle's exact direct solves and closed forms."""
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
 from oracle import fem, step
 from oracle import tableaux as OT
@@ -16,7 +17,7 @@ def _max_rel(gpu_list, ora_list):
     return max(rel(a, b) for a, b in zip(gpu_list, ora_list))
 
 
-@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER, P.PC_RANA_LD])
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER, P.PC_GS_UPPER, P.PC_RANA_LD])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_solve_stages_matches_direct(pc, transpose):
     N, dt = 64, 1e-3
@@ -32,6 +33,61 @@ def test_solve_stages_matches_direct(pc, transpose):
     assert stats["last_rel_resid"] <= 1e-12
     assert rel(host(k), ref) < 1e-9
     assert stats["fgmres_its_total"] > 1
+
+
+@pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER, P.PC_GS_UPPER, P.PC_RANA_LD])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_ia_solve_stages_matches_direct(pc, transpose):
+    # eq:block_struct_IA: (A^{-1} (x) M + dt I (x) K) w = f, or its transpose
+    N, dt = 64, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    otab = OT.radau_iia(3)
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=pc, rtol=1e-12, splitting=P.SPLIT_IA)
+    f = synth.random_stage_block(N, 3, 22).ravel()
+    w, stats = stp.solve_stages(dev(f), transpose=transpose)
+    Acal = step.coupled_matrix_ia(M, K, otab["A"], dt)
+    if transpose:
+        Acal = Acal.T.tocsc()
+    ref = spla.spsolve(Acal, f)
+    y = host(stp.apply_stage_operator(dev(ref), transpose=transpose))
+    assert rel(y, Acal @ ref) < 1e-14
+    assert np.linalg.norm(Acal @ host(w) - f) <= 1.01e-12 * np.linalg.norm(f)
+    assert stats["last_rel_resid"] <= 1e-12
+    assert rel(host(w), ref) < 1e-9
+
+
+@pytest.mark.parametrize("tname,pc,prec,tol", [("gl4", P.PC_GS_LOWER, P.F64, 1e-10), ("gl4", P.PC_RANA_LD, P.F64, 1e-10),
+                                               ("radau3", P.PC_RANA_LD, P.F32, 1e-8),
+                                               ("lobatto", P.PC_GS_LOWER, P.F64, 1e-10),
+                                               ("alexander", P.PC_GS_LOWER, P.F64, 1e-10)])
+def test_ia_advance_matches_oracle(tname, pc, prec, tol):
+    # the IA form integrates the same step: compare with the oracle's IA run (and so with the AI one)
+    N, dt, nsteps = 128, 5e-4, 4
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    otab = {"gl4": OT.gauss_legendre(4), "radau3": OT.radau_iia(3), "lobatto": OT.lobatto_iiic2(),
+            "alexander": OT.alexander()}[tname]
+    ptab = {"gl4": P.tableaux.gauss_legendre(4), "radau3": P.tableaux.radau_iia(3),
+            "lobatto": P.tableaux.lobatto_iiic2(), "alexander": P.tableaux.alexander()}[tname]
+    _, stp = make(N, kap, ptab, dt, precond=pc, rtol=1e-12, splitting=P.SPLIT_IA, mg_precision=prec)
+    u = dev(u0)
+    gpu = []
+    for _ in range(nsteps):
+        stp.advance(u, 1)
+        gpu.append(host(u))
+    ora = step.run(N, kap, otab, dt, nsteps, u0, splitting="IA")[1:]
+    assert _max_rel(gpu, ora) < tol
+
+
+def test_ia_rejects_singular_tableau():
+    N = 16
+    prob = P.Problem(N, dev(np.ones(N * N)))
+    tab = {"A": np.array([[0.5, 0.5], [0.5, 0.5]]), "b": np.array([0.5, 0.5]), "c": np.array([1.0, 1.0])}
+    P.Stepper(prob, tab, 1e-3, precond=P.PC_JACOBI)  # the AI form only needs a_ii > 0
+    with pytest.raises(P.IrkError) as e:
+        P.Stepper(prob, tab, 1e-3, precond=P.PC_JACOBI, splitting=P.SPLIT_IA)
+    assert e.value.code == P.IRK_EINVAL
 
 
 def test_config1_decay():
