@@ -56,6 +56,31 @@ def stages_from_w(A, w):
     return np.linalg.solve(A, np.asarray(w).reshape(s, -1)).ravel()
 
 
+def dirk_solve(M, K, A, dt, rhs, trans=False):
+    """Stage-by-stage solve of the coupled system for a lower-triangular A (Section 2.3, DIRK).
+
+    (I (x) M + dt A (x) K) k = rhs is block lower triangular, so stage i needs one single-stage
+    solve with M + dt a_ii K after moving the already known stages to the right:
+        (M + dt a_ii K) k_i = rhs_i - dt K sum_{j<i} a_ij k_j.
+    The transposed system (A^T upper triangular) runs backwards: j > i with a_ji.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    s = A.shape[0]
+    if np.any(np.triu(A, 1) != 0.0):
+        raise ValueError("DIRK needs a lower-triangular A")
+    R = np.asarray(rhs).reshape(s, -1)
+    k = np.zeros_like(R)
+    order = range(s - 1, -1, -1) if trans else range(s)
+    for i in order:
+        known = range(i + 1, s) if trans else range(i)
+        t = R[i].copy()
+        for j in known:
+            aij = A[j, i] if trans else A[i, j]
+            t -= dt * (K @ (aij * k[j]))
+        k[i] = spla.spsolve((M + dt * A[i, i] * K).tocsc(), t)
+    return k.ravel()
+
+
 def stage_rhs(K, u, s, F=None):
     """Right-hand side f_i = -K u^n + F_i, identical for every stage when F is constant in time."""
     f = -(K @ u)
@@ -172,7 +197,8 @@ def dense_solve(M, K, A, dt, rhs):
 def run(N, kappa, tab, dt, nsteps, u0, F=None, tier="coupled", return_stages=False, splitting="AI"):
     """Integrate nsteps steps; returns the list [u^0, u^1, ..., u^nsteps] (and the stage unknowns).
 
-    tier: "coupled" (tier 2), "decoupled" (tier 3, AI only) or "dense" (tier 1).
+    tier: "coupled" (tier 2), "decoupled" (tier 3, AI only), "dense" (tier 1) or "dirk" (stage-by-stage
+    single-stage solves for a lower-triangular A, AI only).
     splitting: "AI" solves eq:block_struct_AI for k; "IA" solves eq:block_struct_IA for w and
     recovers k = (A^{-1} (x) I) w for the update (the stage unknowns returned are then w).
     """
@@ -197,6 +223,8 @@ def run(N, kappa, tab, dt, nsteps, u0, F=None, tier="coupled", return_stages=Fal
     elif tier == "dense":
         Ad = coupled_matrix(M, K, A, dt).toarray()
         solver = lambda r, trans=False: np.linalg.solve(Ad.T if trans else Ad, r)  # noqa: E731
+    elif tier == "dirk":
+        solver = lambda r: dirk_solve(M, K, A, dt, r)  # noqa: E731
     else:
         raise ValueError(tier)
     us = [np.asarray(u0, dtype=np.float64).copy()]

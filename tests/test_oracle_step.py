@@ -130,6 +130,25 @@ def test_dirk_sequential_solve():
         r = -(K @ (u + dt * sum(A[i, j] * kk[j] for j in range(i))))
         kk.append(spla.spsolve((M + dt * A[i, i] * K).tocsc(), r))
     assert np.linalg.norm(k - np.concatenate(kk)) < 1e-12 * np.linalg.norm(k)
+    # the oracle's stage-by-stage tier, forward and transposed, against the coupled LU
+    assert np.linalg.norm(step.dirk_solve(M, K, A, dt, step.stage_rhs(K, u, 3)) - k) < 1e-12 * np.linalg.norm(k)
+    f = np.random.default_rng(8).standard_normal(3 * (N - 1) ** 2)
+    kt = step.CoupledLU(M, K, A, dt).solve(f, trans=True)
+    assert np.linalg.norm(step.dirk_solve(M, K, A, dt, f, trans=True) - kt) < 1e-12 * np.linalg.norm(kt)
+    with pytest.raises(ValueError):
+        step.dirk_solve(M, K, T.radau_iia(2)["A"], dt, f[: 2 * (N - 1) ** 2])
+
+
+@pytest.mark.parametrize("tabname", ["alexander", "wso433"])
+def test_dirk_tier_matches_closed_form(tabname):
+    # kappa = 1, sine modes: u_n = sum alpha_jk R(-dt lam_jk)^n phi_jk with R of the DIRK tableau
+    tab = {"alexander": T.alexander(), "wso433": T.wsodirk433()}[tabname]
+    N, dt, nsteps = 16, 1e-2, 5
+    u0, amps = synth.sine_modes_u0(N, 0)
+    us = step.run(N, None, tab, dt, nsteps, u0, tier="dirk")
+    cf = step.closed_form_modes(N, tab, dt, nsteps, amps)
+    for n in range(nsteps + 1):
+        assert np.linalg.norm(us[n] - cf[n]) <= 1e-12 * np.linalg.norm(cf[n])
 
 
 # ---------------------------------------------------------------- IA splitting (eq:butcherw, eq:block_struct_IA)
