@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="time steps in the CPU oracle sample")
     ap.add_argument("--precond", choices=["gs", "jacobi", "rana", "gsu"], default="gs")
+    ap.add_argument("--tableau", choices=["radau3", "radau1", "radau2", "radau4", "gl4", "alexander", "wso433"],
+                    default="radau3", help="Butcher tableau (the headline workload is radau3)")
+    ap.add_argument("--stage-type", choices=["coupled", "dirk"], default="coupled",
+                    help="one coupled stage solve, or stage-by-stage solves for a DIRK tableau")
     ap.add_argument("--splitting", choices=["ai", "ia"], default="ai",
                     help="stage formulation: eq:block_struct_AI (k) or eq:block_struct_IA (w = A k)")
     ap.add_argument("--orth", choices=["cgs2", "selective"], default="cgs2")
@@ -67,6 +71,7 @@ def solver_options(P, args):
                 orth={"cgs2": P.ORTH_CGS2, "selective": P.ORTH_CGS_SELECTIVE}[args.orth],
                 initial_guess={"zero": P.GUESS_ZERO, "prev": P.GUESS_PREV}[args.guess],
                 splitting={"ai": P.SPLIT_AI, "ia": P.SPLIT_IA}[args.splitting],
+                stage_type={"coupled": P.STAGE_COUPLED, "dirk": P.STAGE_DIRK}[args.stage_type],
                 restart=args.restart, mg_coarse_n=args.coarse_n, rtol=1e-10)
 
 
@@ -89,7 +94,14 @@ def timed_run(P, torch, prob, tab, dt, u0_dev, steps, warmup, prec, opts):
     return stp, u, ev0.elapsed_time(ev1), stats, setup_s
 
 
-def golden_error(u, steps):
+def make_tableau(P, name):
+    T = P.tableaux
+    return {"radau1": lambda: T.radau_iia(1), "radau2": lambda: T.radau_iia(2), "radau3": lambda: T.radau_iia(3),
+            "radau4": lambda: T.radau_iia(4), "gl4": lambda: T.gauss_legendre(4), "alexander": T.alexander,
+            "wso433": T.wsodirk433}[name]()
+
+
+def golden_error(u, steps, tableau="radau3"):
     """Relative L2 error of u against the oracle's full-size result (sketch estimate), or None."""
     import numpy as np
 
@@ -100,7 +112,7 @@ def golden_error(u, steps):
     with open(GOLDEN) as f:
         g = json.load(f)
     ref = g["steps"].get(str(steps))
-    if ref is None or g["n"] != u.size:
+    if ref is None or g["n"] != u.size or g.get("tableau") != tableau:
         return None
     G = synth.sketch_vectors(g["n"], g["n_sketch"], g["sketch_seed"])
     idx = np.asarray(g["indices"])
@@ -180,12 +192,12 @@ def main():
         del a, b
     N = args.N
     n = (N - 1) ** 2
-    s = 3
+    tab = make_tableau(P, args.tableau)
+    s = len(tab["b"])
     dt = 1e-3
     kap = synth.grf_kappa(N, 1)
     u0, _ = synth.sine_modes_u0(N, 0)
     prob = P.Problem(N, torch.as_tensor(kap).cuda())
-    tab = P.tableaux.radau_iia(3)
     u0d = torch.as_tensor(u0).cuda()
     prec = {"f32": P.F32, "bf16": P.BF16, "f64": P.F64}[args.precision]
     opts = solver_options(P, args)
@@ -205,24 +217,26 @@ def main():
         "vs_baseline": None,
         "dtype": {"f32": "f64+f32", "bf16": "f64+bf16", "f64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"diffusion Q1 {N}x{N}, kappa=exp(GRF seed 1), RadauIIA(3), dt=1e-3, "
+        "config": {"workload": f"diffusion Q1 {N}x{N}, kappa=exp(GRF seed 1), {tab['name']}, dt=1e-3, "
                                f"FGMRES({args.restart}) rtol 1e-10, P_{ {'gs': 'L', 'jacobi': 'D', 'rana': 'LD', 'gsu': 'U'}[args.precond]} + "
                                f"1 GMG V-cycle Cheb(2), MG {args.precision}"
-                               + (", IA splitting" if args.splitting == "ia" else ""),
+                               + (", IA splitting" if args.splitting == "ia" else "")
+                               + (", DIRK stage-by-stage solves" if args.stage_type == "dirk" else ""),
                    "N": N, "dofs": n, "stages": s},
         "fgmres_its_per_step": stats["fgmres_its_total"] / max(1, args.steps),
         "setup_s": setup_s,
-        "solver": {"precond": args.precond, "splitting": args.splitting, "orth": args.orth, "guess": args.guess,
+        "solver": {"tableau": args.tableau, "stage_type": args.stage_type, "precond": args.precond,
+                   "splitting": args.splitting, "orth": args.orth, "guess": args.guess,
                    "restart": args.restart,
                    "coarse_n": args.coarse_n},
-        "error_vs_oracle": golden_error(uh, args.steps),
+        "error_vs_oracle": golden_error(uh, args.steps, args.tableau),
     }
     if not args.no_fp64 and prec != P.F64:
         _, u64, ms64, st64, _ = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, P.F64, opts)
         u64h = u64.cpu().numpy()
         out["fp64"] = {"value": n * s * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                        "fgmres_its_per_step": st64["fgmres_its_total"] / max(1, args.steps),
-                       "error_vs_oracle": golden_error(u64h, args.steps)}
+                       "error_vs_oracle": golden_error(u64h, args.steps, args.tableau)}
         out["mixed_over_fp64"] = value / out["fp64"]["value"]
         out["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(uh - u64h) / np.linalg.norm(u64h))
     if not args.no_roofline:

@@ -68,6 +68,10 @@ enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial gu
  * IA solves eq:block_struct_IA, (A^{-1} (x) M + dt I (x) K) w = f, for w = (A (x) I) k
  * (eq:butcherw, eq:stageeqw); A must then be invertible. */
 enum { IRK_SPLIT_AI = 0, IRK_SPLIT_IA = 1 };
+/* Stage solve (Section 2.3): COUPLED runs one FGMRES on the whole stage system; DIRK (lower-
+ * triangular A, AI form) solves the stages one after the other, each by FGMRES on
+ * M + dt a_ii K preconditioned by one V-cycle, with the known stages moved to the right. */
+enum { IRK_STAGE_COUPLED = 0, IRK_STAGE_DIRK = 1 };
 
 /* Butcher tableau (Section 2): A is s x s row-major, b and c have s entries.
  * Host memory; copied at stepper creation. */
@@ -95,6 +99,7 @@ typedef struct {
   int use_graphs;     /* 1: replay each Krylov iteration as a captured HIP graph;  
                          0: launch every kernel eagerly (same arithmetic)          */
   int splitting;      /* IRK_SPLIT_AI (default) or IRK_SPLIT_IA                    */
+  int stage_type;     /* IRK_STAGE_COUPLED (default) or IRK_STAGE_DIRK             */
 } irk_options;
 
 /* Per-call statistics (host struct, filled if non-NULL). */
@@ -138,8 +143,8 @@ int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *
  * multigrid hierarchy (level diffusivities, power-iteration estimates of mu per
  * level and diagonal block, the coarsest-level inverse) and the Krylov
  * workspace. Every eigenvalue of A must have positive real part and every
- * a_ii > 0 (Rana-LD: every LDU pivot > 0), and A must be invertible for IRK_SPLIT_IA
- * (IRK_EINVAL otherwise). The problem must outlive the stepper. */
+ * a_ii > 0 (Rana-LD: every LDU pivot > 0), A must be invertible for IRK_SPLIT_IA and
+ * lower triangular for IRK_STAGE_DIRK (IRK_EINVAL otherwise). The problem must outlive the stepper. */
 int irk_stepper_create(irk_stepper **out, const irk_problem *p, const irk_tableau *tab,
                        double dt, const irk_options *opts, void *stream);
 void irk_stepper_destroy(irk_stepper *st);
@@ -169,7 +174,9 @@ int irk_vcycle(const irk_stepper *st, int stage, const double *t, double *z, voi
 
 /* a5: solve (I (x) M + dt*A (x) K) k = f (A^T when transpose != 0) by FGMRES to the
  * stepper's rtol from a zero initial guess; with IRK_SPLIT_IA the unknown is w and the
- * operator that of irk_apply_stage_operator. f, k: device s*n. Synchronises. */
+ * operator that of irk_apply_stage_operator. With IRK_STAGE_DIRK the same system is solved
+ * stage by stage (backwards for the transpose), each stage to rtol of its own right-hand
+ * side; stats count one solve per stage. f, k: device s*n. Synchronises. */
 int irk_solve_stages(irk_stepper *st, const double *f, double *k, int transpose, irk_stats *stats, void *stream);
 
 /* a1+a5+a6: advance u (device n, in/out) by nsteps time steps of size dt with forcing F

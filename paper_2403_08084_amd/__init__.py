@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libirk.so")
 IRK_OK, IRK_EINVAL, IRK_ENOMEM, IRK_EHIP, IRK_ENOCONV, IRK_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 PC_JACOBI, PC_GS_LOWER, PC_RANA_LD, PC_GS_UPPER = 0, 1, 2, 3
 SPLIT_AI, SPLIT_IA = 0, 1
+STAGE_COUPLED, STAGE_DIRK = 0, 1
 F64, F32, BF16 = 0, 1, 2
 ORTH_CGS2, ORTH_CGS_SELECTIVE = 0, 1
 GUESS_ZERO, GUESS_PREV = 0, 1
@@ -55,6 +56,7 @@ class Options(ctypes.Structure):
         ("initial_guess", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
         ("splitting", ctypes.c_int),
+        ("stage_type", ctypes.c_int),
     ]
 
 

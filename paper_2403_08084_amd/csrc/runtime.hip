@@ -130,7 +130,11 @@ struct irk_stepper {
   size_t timer_used = 0;
   double timer_bytes = 0;
   int timer_launches = 0;
-  std::vector<hipGraphExec_t> graphs[2];  // one per Arnoldi index j, forward / transposed
+  // one graph per Arnoldi index j, per system: [0] coupled forward, [1] coupled transposed,
+  // [2 + i] the single-stage system of DIRK stage i
+  std::vector<hipGraphExec_t> graphs[2 + kMaxStages];
+  bool dirk = false;  // stage-by-stage solves for a lower-triangular A (Section 2.3)
+  int sys = -1;       // system the Krylov solver works on: -1 the coupled one, i >= 0 DIRK stage i
 };
 
 namespace {
@@ -140,6 +144,9 @@ double* res_slot(irk_stepper* st, int which) { return st->dres + (long)which * R
 double* sigma_dev(irk_stepper* st) { return st->dres + 4L * RSTRIDE; }
 double* ycoef_dev(irk_stepper* st) { return st->dres + 5L * RSTRIDE; }
 constexpr long DRES_LEN = 6L * RSTRIDE;
+
+// length of the Krylov vectors of the current system
+long sys_len(const irk_stepper* st) { return st->sys < 0 ? st->vlen : st->g.plane; }
 
 // stage-operator mixing coefficients for the forward or transposed system
 Coefs coefs_of(const irk_stepper* st, bool trans) {
@@ -224,7 +231,7 @@ int timer_pair(irk_stepper* st, int family, hipEvent_t* e0, hipEvent_t* e1) {
 // Algorithmic bytes of one streaming Gram-Schmidt pass over s*n interior values:
 // the basis vectors it reads, w read, and w written when it updates w.
 double ortho_bytes(const irk_stepper* st, const OrthoArgs& a) {
-  const double vec = 8.0 * st->s * (double)(st->prob->N - 1) * (st->prob->N - 1);
+  const double vec = 8.0 * (double)(a.len / st->g.plane) * (double)(st->prob->N - 1) * (st->prob->N - 1);
   const bool ax = a.coef != nullptr, dt = a.want_dots != 0;
   const int nvec = (a.nv > 0 && (ax || dt)) ? a.nv : 0;
   return vec * (nvec + 1 + (ax ? 1 : 0));
@@ -232,8 +239,8 @@ double ortho_bytes(const irk_stepper* st, const OrthoArgs& a) {
 
 int ortho(irk_stepper* st, const OrthoArgs& a, hipStream_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  // only passes over full stage blocks are timed (not the setup's per-level norms)
-  if (a.len == st->vlen) {
+  // only passes over the Krylov vectors are timed (not the setup's per-level norms)
+  if (a.len == sys_len(st)) {
     CHK(timer_pair(st, 0, &e0, &e1));
     if (e0) st->timer_bytes += ortho_bytes(st, a);
   }
@@ -440,6 +447,11 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
       }
     }
   }
+  // the power iterations used tmp / tmp2 with coarse-level layouts: restore the all-zero boundary ring and
+  // padding of the finest layout, which the interior-only kernels writing into them rely on
+  const size_t tb = (size_t)std::max(st->s, 2) * st->g.plane * sizeof(double);
+  HIPCHK(hipMemsetAsync(st->tmp, 0, tb, s));
+  HIPCHK(hipMemsetAsync(st->tmp2, 0, tb, s));
   // coarsest-level inverses
   const Level& lc = st->lv[L - 1];
   std::vector<double> kpad((size_t)lc.g.N * lc.g.pitch), kc((size_t)lc.g.N * lc.g.N);
@@ -496,6 +508,7 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
 // IA form: P = Atil^{-1} (x) M + dt I (x) K, z_i = atil_ii B_i^{-1} (v_i - M sum_j c_ij z_j) with
 // C = Atil^{-1}, B_i = M + dt atil_ii K (one V-cycle is linear, so atil_ii scales its input).
 int precondition(irk_stepper* st, const double* v, const double* vscale, double* z, bool trans, hipStream_t s) {
+  if (st->sys >= 0) return vcycle(st, st->sys, v, vscale, z, s);  // one DIRK stage: one V-cycle
   const long plane = st->g.plane;
   const int ns = st->s;
   const Coefs a = ptil_of(st, trans);
@@ -542,6 +555,13 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
 }
 
 int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s) {
+  if (st->sys >= 0) {
+    // one DIRK stage: M + dt a_ii K (symmetric)
+    Coefs a{};
+    a.a[0] = st->A[st->sys * st->s + st->sys];
+    launch_stage_operator(x, y, f, st->prob->kappa, st->g, 1, a, st->dt, s);
+    return check_launch();
+  }
   launch_stage_operator(x, y, f, st->prob->kappa, st->g, st->s, coefs_of(st, trans), st->dt, s, st->ia);
   return check_launch();
 }
@@ -553,7 +573,7 @@ int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool 
 // with re-orthogonalisation (passes A, B, C) against V_0..V_j. Scales are read
 // from device memory, so the sequence is replayable as a graph.
 int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
-  const long n = st->vlen;
+  const long n = sys_len(st);
   double* sig = sigma_dev(st);
   double* Vj = st->V + (long)j * n;
   double* Vn = st->V + (long)(j + 1) * n;
@@ -594,7 +614,7 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
 // Enqueue Arnoldi step j on s: replay its captured graph (captured on first use), or eagerly.
 int run_arnoldi(irk_stepper* st, int j, bool trans, hipStream_t s) {
   if (!st->opt.use_graphs || st->timer_family >= 0) return arnoldi_body(st, j, trans, s);
-  std::vector<hipGraphExec_t>& gs = st->graphs[trans ? 1 : 0];
+  std::vector<hipGraphExec_t>& gs = st->graphs[st->sys >= 0 ? 2 + st->sys : (trans ? 1 : 0)];
   if (gs.empty()) gs.assign(st->opt.restart, nullptr);
   if (!gs[j]) {
     HIPCHK(hipStreamBeginCapture(st->cap, hipStreamCaptureModeRelaxed));
@@ -621,12 +641,16 @@ int run_arnoldi(irk_stepper* st, int j, bool trans, hipStream_t s) {
 struct SolveInfo {
   int its = 0, restarts = 0;
   double rel = 0;
+  int solves = 0, its_max = 0;
 };
 
-// Solve Acal k = f (padded planes). If use_guess, st->k holds the initial guess.
-int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s) {
+// Solve Acal x = f (padded planes) for the current system; x defaults to st->k. If use_guess, x holds
+// the initial guess.
+int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s,
+           double* x = nullptr) {
   const int m = st->opt.restart;
-  const long n = st->vlen;
+  const long n = sys_len(st);
+  if (!x) x = st->k;
   double* sig = sigma_dev(st);
   double* h = st->hres;
   info = SolveInfo{};
@@ -637,14 +661,14 @@ int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveIn
   const double fnorm = std::sqrt(h[0]);
   if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
   if (fnorm == 0.0) {
-    HIPCHK(hipMemsetAsync(st->k, 0, n * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
     return IRK_OK;
   }
   // initial residual into V_0
   if (use_guess) {
-    CHK(apply_op(st, st->k, st->V, f, trans, s));
+    CHK(apply_op(st, x, st->V, f, trans, s));
   } else {
-    HIPCHK(hipMemsetAsync(st->k, 0, n * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(st->V, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   CHK(norm2(st, st->V, n, res_slot(st, 0), sig, s));
@@ -719,7 +743,7 @@ int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveIn
       a.V = st->Z;
       a.vstride = n;
       a.nv = jdone;
-      a.w = st->k;
+      a.w = x;
       a.len = n;
       a.coef = ycoef_dev(st);
       a.coef_sign = -1.0;
@@ -727,7 +751,7 @@ int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveIn
       CHK(ortho(st, a, s));
     }
     // true residual r = f - Acal k into V_0
-    CHK(apply_op(st, st->k, st->V, f, trans, s));
+    CHK(apply_op(st, x, st->V, f, trans, s));
     CHK(norm2(st, st->V, n, res_slot(st, 0), sig, s));
     HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -749,10 +773,45 @@ int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveIn
 void add_stats(irk_stats* stats, const SolveInfo& si) {
   if (!stats) return;
   stats->fgmres_its_total += si.its;
-  stats->fgmres_its_max = std::max(stats->fgmres_its_max, si.its);
+  stats->fgmres_its_max = std::max(stats->fgmres_its_max, std::max(si.its_max, si.solves ? 0 : si.its));
   stats->restarts_total += si.restarts;
-  stats->solves += 1;
+  stats->solves += std::max(1, si.solves);
   stats->last_rel_resid = si.rel;
+}
+
+// Solve the stage system (I (x) M + dt A (x) K) k = f (A^T if trans) into st->k: one FGMRES on the coupled
+// system, or, for a DIRK stepper, block substitution with one single-stage FGMRES per stage (Section 2.3):
+// (M + dt a_ii K) k_i = f_i - dt K sum_{j<i} a_ij k_j (transposed: backwards, j > i with a_ji).
+int stage_solve(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s) {
+  if (!st->dirk) return fgmres(st, f, trans, use_guess, info, s);
+  info = SolveInfo{};
+  const int ns = st->s;
+  const long plane = st->g.plane;
+  for (int step = 0; step < ns; ++step) {
+    const int i = trans ? ns - 1 - step : step;
+    const int j0 = trans ? i + 1 : 0;
+    const double* rhs = f + i * plane;
+    if (step > 0) {
+      Coefs row{};
+      for (int q = 0; q < step; ++q)
+        row.a[q] = trans ? st->A[(j0 + q) * ns + i] : st->A[i * ns + j0 + q];
+      launch_gs_couple(f + i * plane, nullptr, st->k + j0 * plane, step, row, st->dt, st->prob->kappa, st->tmp2,
+                       st->g, s);
+      CHK(check_launch());
+      rhs = st->tmp2;
+    }
+    SolveInfo si;
+    st->sys = i;
+    const int rc = fgmres(st, rhs, false, use_guess, si, s, st->k + i * plane);
+    st->sys = -1;
+    info.its += si.its;
+    info.restarts += si.restarts;
+    info.its_max = std::max(info.its_max, si.its);
+    info.rel = std::max(info.rel, si.rel);
+    info.solves++;
+    if (rc != IRK_OK) return rc;
+  }
+  return IRK_OK;
 }
 
 void init_stats(irk_stats* stats) {
@@ -765,7 +824,7 @@ void init_stats(irk_stats* stats) {
 int forward_step(irk_stepper* st, const double* Fp, SolveInfo& si, hipStream_t s) {
   launch_stage_rhs(st->u, Fp, st->f, st->prob->kappa, st->g, st->s, s);
   const bool guess = st->opt.initial_guess == IRK_GUESS_PREV && st->have_prev;
-  CHK(fgmres(st, st->f, false, guess, si, s));
+  CHK(stage_solve(st, st->f, false, guess, si, s));
   st->have_prev = true;
   launch_update(st->u, st->k, st->s, b_of(st), st->dt, st->g, s);
   return check_launch();
@@ -875,6 +934,7 @@ void irk_options_default(irk_options* o) {
   o->initial_guess = IRK_GUESS_ZERO;
   o->use_graphs = 1;
   o->splitting = IRK_SPLIT_AI;
+  o->stage_type = IRK_STAGE_COUPLED;
 }
 
 int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stream) {
@@ -1018,6 +1078,13 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
     return fail(IRK_EINVAL, "unknown initial_guess");
   if (o.mg_coarse_n < 1) return fail(IRK_EINVAL, "mg_coarse_n must be >= 1");
   if (o.splitting != IRK_SPLIT_AI && o.splitting != IRK_SPLIT_IA) return fail(IRK_EINVAL, "unknown splitting");
+  if (o.stage_type != IRK_STAGE_COUPLED && o.stage_type != IRK_STAGE_DIRK) return fail(IRK_EINVAL, "unknown stage_type");
+  if (o.stage_type == IRK_STAGE_DIRK) {
+    if (o.splitting != IRK_SPLIT_AI) return fail(IRK_EINVAL, "the DIRK stage type solves the AI form");
+    for (int i = 0; i < tab->s; ++i)
+      for (int j = i + 1; j < tab->s; ++j)
+        if (tab->A[i * tab->s + j] != 0.0) return fail(IRK_EINVAL, "the DIRK stage type needs a lower-triangular A");
+  }
   const int s = tab->s;
   for (int i = 0; i < s * s; ++i)
     if (!std::isfinite(tab->A[i])) return fail(IRK_EINVAL, "non-finite tableau entry");
@@ -1081,6 +1148,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
     for (int i = 0; i < s; ++i) st->pd[i] = st->Pt[0][i * s + i];
   }
   st->ia = o.splitting == IRK_SPLIT_IA;
+  st->dirk = o.stage_type == IRK_STAGE_DIRK;
   {
     double Ainv[kMaxStages * kMaxStages];
     if (st->ia && !small_inverse(tab->A, s, Ainv)) {
@@ -1228,7 +1296,7 @@ int irk_solve_stages(irk_stepper* st, const double* f, double* k, int transpose,
   launch_pack(f, st->f, st->g, st->s, s);
   CHK(check_launch());
   SolveInfo si;
-  const int rc = fgmres(st, st->f, transpose != 0, false, si, s);
+  const int rc = stage_solve(st, st->f, transpose != 0, false, si, s);
   add_stats(stats, si);
   if (rc != IRK_OK) {
     if (stats) stats->failed_step = 0;
@@ -1347,7 +1415,7 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
       // reverse step act.arg from u_n = st->u: recompute its stages, then the adjoint step
       SolveInfo si;
       launch_stage_rhs(st->u, nullptr, st->f, st->prob->kappa, g, st->s, s);
-      rc = fgmres(st, st->f, false, false, si, s);
+      rc = stage_solve(st, st->f, false, false, si, s);
       add_stats(stats, si);
       if (rc != IRK_OK) break;
       if (hipMemcpyAsync(kstep, st->k, st->vlen * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
@@ -1356,7 +1424,7 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
       }
       launch_adjoint_rhs(lam, st->f, st->s, bb, st->dt, g, s);
       SolveInfo sa;
-      rc = fgmres(st, st->f, true, false, sa, s);
+      rc = stage_solve(st, st->f, true, false, sa, s);
       add_stats(stats, sa);
       if (rc != IRK_OK) break;
       if (hipMemcpyAsync(nu, st->k, st->vlen * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {

@@ -36,6 +36,20 @@ def test_adjoint_matches_oracle(nsnap, split, pc):
     assert st["forward_advances"] == revolve.min_advances_dp(nsteps, min(nsnap, nsteps))
 
 
+def test_dirk_adjoint_matches_oracle():
+    # stage-by-stage forward solves and backward (transposed) stage solves for WSODIRK433
+    N, nsteps, dt = 32, 5, 1e-3
+    kap, u0, ustar = _setup(N, nsteps, dt)
+    tab = OT.wsodirk433()
+    fwd = adjoint.forward(N, kap, tab, dt, nsteps, u0)
+    _, lamN = adjoint.objective(fwd[2], fwd[0][-1], ustar)
+    lam0_o, g_o = adjoint.gradient(N, kap, tab, dt, nsteps, u0, lamN, fwd=fwd)
+    _, stp = make(N, kap, P.tableaux.wsodirk433(), dt, rtol=1e-13, stage_type=P.STAGE_DIRK)
+    lam0, g, st = stp.adjoint(dev(u0), nsteps, 2, dev(lamN))
+    assert rel(host(lam0), lam0_o) < 1e-9
+    assert rel(host(g), g_o) < 1e-9
+
+
 def test_revolve_equals_store_all_bitwise():
     N, nsteps, dt = 32, 7, 1e-3
     kap, u0, ustar = _setup(N, nsteps, dt)

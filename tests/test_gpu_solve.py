@@ -279,3 +279,70 @@ def test_graph_replay_matches_eager_bitwise(prec):
         outs.append((host(u), host(u2)))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[1][0], outs[1][1])
+
+
+# ---------------------------------------------------------------- DIRK stage type (Section 2.3)
+
+_DIRK = {"alexander": (OT.alexander, P.tableaux.alexander), "wso433": (OT.wsodirk433, P.tableaux.wsodirk433)}
+
+
+@pytest.mark.parametrize("tname", ["alexander", "wso433"])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("N", [64, 128])
+def test_dirk_solve_stages_matches_direct(tname, transpose, N):
+    # N = 128 has three multigrid levels: the coarse-level power iterations share the stage right-hand side's
+    # scratch buffer, whose fine-layout boundary and padding must be zero again afterwards
+    dt = 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    otab, ptab = _DIRK[tname][0](), _DIRK[tname][1]()
+    s = otab["A"].shape[0]
+    _, stp = make(N, kap, ptab, dt, rtol=1e-12, stage_type=P.STAGE_DIRK)
+    f = synth.random_stage_block(N, s, 23).ravel()
+    k, stats = stp.solve_stages(dev(f), transpose=transpose)
+    ref = step.CoupledLU(M, K, otab["A"], dt).solve(f, trans=transpose)
+    assert stats["solves"] == s and stats["fgmres_its_total"] >= s
+    assert rel(host(k), ref) < 1e-10
+
+
+@pytest.mark.parametrize("tname,prec,tol", [("alexander", P.F64, 1e-10), ("wso433", P.F64, 1e-10),
+                                            ("wso433", P.F32, 1e-8)])
+def test_dirk_advance_matches_oracle(tname, prec, tol):
+    N, dt, nsteps = 128, 1e-3, 4
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    otab, ptab = _DIRK[tname][0](), _DIRK[tname][1]()
+    _, stp = make(N, kap, ptab, dt, rtol=1e-12, stage_type=P.STAGE_DIRK, mg_precision=prec)
+    u = dev(u0)
+    gpu = []
+    for _ in range(nsteps):
+        stp.advance(u, 1)
+        gpu.append(host(u))
+    ora = step.run(N, kap, otab, dt, nsteps, u0, tier="dirk")[1:]
+    assert _max_rel(gpu, ora) < tol
+
+
+def test_dirk_closed_form_and_coupled_agree():
+    # kappa = 1: u_n = sum alpha R(-dt lam)^n phi with the DIRK's stability function; the coupled solve of
+    # the same tableau (P_L, exact up to the V-cycles) gives the same steps
+    N, dt, nsteps = 64, 2e-3, 5
+    u0, amps = synth.sine_modes_u0(N, 0)
+    kap = np.ones(N * N)
+    cf = step.closed_form_modes(N, OT.alexander(), dt, nsteps, amps)
+    outs = {}
+    for st_type in (P.STAGE_DIRK, P.STAGE_COUPLED):
+        _, stp = make(N, kap, P.tableaux.alexander(), dt, rtol=1e-12, stage_type=st_type)
+        u = dev(u0)
+        stp.advance(u, nsteps)
+        outs[st_type] = host(u)
+        assert rel(outs[st_type], cf[nsteps]) < 1e-10
+    assert rel(outs[P.STAGE_DIRK], outs[P.STAGE_COUPLED]) < 1e-10
+
+
+def test_dirk_rejects_full_tableau_and_ia():
+    N = 16
+    prob = P.Problem(N, dev(np.ones(N * N)))
+    for tab, opts in ((P.tableaux.radau_iia(3), {}), (P.tableaux.alexander(), {"splitting": P.SPLIT_IA})):
+        with pytest.raises(P.IrkError) as e:
+            P.Stepper(prob, tab, 1e-3, stage_type=P.STAGE_DIRK, **opts)
+        assert e.value.code == P.IRK_EINVAL
