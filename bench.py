@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="time steps in the CPU oracle sample")
-    ap.add_argument("--precond", choices=["gs", "jacobi", "rana", "gsu"], default="gs")
+    ap.add_argument("--precond", choices=["gs", "jacobi", "rana", "gsu", "mmg"], default="gs")
     ap.add_argument("--tableau", choices=["radau3", "radau1", "radau2", "radau4", "gl4", "alexander", "wso433"],
                     default="radau3", help="Butcher tableau (the headline workload is radau3)")
     ap.add_argument("--stage-type", choices=["coupled", "dirk"], default="coupled",
@@ -67,7 +67,8 @@ def parse():
 
 
 def solver_options(P, args):
-    return dict(precond={"gs": P.PC_GS_LOWER, "jacobi": P.PC_JACOBI, "rana": P.PC_RANA_LD, "gsu": P.PC_GS_UPPER}[args.precond],
+    return dict(precond={"gs": P.PC_GS_LOWER, "jacobi": P.PC_JACOBI, "rana": P.PC_RANA_LD, "gsu": P.PC_GS_UPPER,
+                          "mmg": P.PC_MONOLITHIC}[args.precond],
                 orth={"cgs2": P.ORTH_CGS2, "selective": P.ORTH_CGS_SELECTIVE}[args.orth],
                 initial_guess={"zero": P.GUESS_ZERO, "prev": P.GUESS_PREV}[args.guess],
                 splitting={"ai": P.SPLIT_AI, "ia": P.SPLIT_IA}[args.splitting],
@@ -218,8 +219,10 @@ def main():
         "dtype": {"f32": "f64+f32", "bf16": "f64+bf16", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"diffusion Q1 {N}x{N}, kappa=exp(GRF seed 1), {tab['name']}, dt=1e-3, "
-                               f"FGMRES({args.restart}) rtol 1e-10, P_{ {'gs': 'L', 'jacobi': 'D', 'rana': 'LD', 'gsu': 'U'}[args.precond]} + "
-                               f"1 GMG V-cycle Cheb(2), MG {args.precision}"
+                               f"FGMRES({args.restart}) rtol 1e-10, " + (
+                                   "1 monolithic GMG V-cycle Cheb(2)" if args.precond == "mmg" else
+                                   f"P_{ {'gs': 'L', 'jacobi': 'D', 'rana': 'LD', 'gsu': 'U'}[args.precond]} + "
+                                   "1 GMG V-cycle Cheb(2)") + f", MG {args.precision}"
                                + (", IA splitting" if args.splitting == "ia" else "")
                                + (", DIRK stage-by-stage solves" if args.stage_type == "dirk" else ""),
                    "N": N, "dofs": n, "stages": s},

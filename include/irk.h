@@ -59,8 +59,9 @@ typedef enum {
   IRK_EBREAKDOWN = -5   /* non-finite value met inside the Krylov iteration    */
 } irk_status;
 
-/* eq:pcbjac, eq:pcbgs, eq:pcranald, and the block upper-triangular variant of eq:pcbgs (Section 3.1) */
-enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2, IRK_PC_GS_UPPER = 3 };
+/* eq:pcbjac, eq:pcbgs, eq:pcranald, the block upper-triangular variant of eq:pcbgs (Section 3.1),
+ * and one monolithic multigrid V-cycle on the whole stage-coupled system (Section 3.3) */
+enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2, IRK_PC_GS_UPPER = 3, IRK_PC_MONOLITHIC = 4 };
 enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precision */
 enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1 };    /* Gram-Schmidt variant */
 enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial guess */
@@ -84,7 +85,8 @@ typedef struct {
 
 /* Solver options; fill with irk_options_default() and override fields. */
 typedef struct {
-  int precond;        /* IRK_PC_JACOBI, IRK_PC_GS_LOWER, IRK_PC_RANA_LD, IRK_PC_GS_UPPER */
+  int precond;        /* IRK_PC_JACOBI, IRK_PC_GS_LOWER, IRK_PC_RANA_LD, IRK_PC_GS_UPPER,
+                         IRK_PC_MONOLITHIC (s <= 4)                                */
   double rtol;        /* stop when |f - Acal k|_2 <= rtol * |f|_2 (true residual)  */
   int restart;        /* FGMRES restart length m, 1..32                           */
   int max_it;         /* total FGMRES iterations allowed per stage solve          */
@@ -163,8 +165,12 @@ int irk_apply_stage_operator(const irk_stepper *st, const double *x, double *y, 
  * P = I (x) M + dt Atil (x) K, stages coupled through K. IA splitting (the printed form):
  * P = Atil^{-1} (x) M + dt I (x) K, stages coupled through M, diagonal blocks
  * (1/atil_ii) M + dt K, whose V-cycle is atil_ii times the V-cycle of M + dt atil_ii K.
- * With transpose != 0 the preconditioner of the transposed system (built from A^T) is
- * applied. v, z: device s*n. */
+ * IRK_PC_MONOLITHIC: one monolithic V-cycle (Section 3.3, eq:Cinv on the patches of
+ * eq:bigdecomp) on the whole system: additive Schwarz over each vertex's s stage values
+ * (an s x s solve per node) inside Chebyshev smoothing, stage-wise transfers, a dense
+ * solve on the coarsest level (halving while N is even and N > mg_coarse_n or
+ * s (N-1)^2 > 1024). With transpose != 0 the preconditioner of the transposed system
+ * (built from A^T) is applied. v, z: device s*n. */
 int irk_apply_preconditioner(const irk_stepper *st, const double *v, double *z, int transpose, void *stream);
 
 /* a4 (Section 3.1 diagonal blocks): z = one V-cycle for (M + dt*atil_ii*K) z = t with zero
@@ -208,6 +214,11 @@ int irk_stepper_sizes(const irk_stepper *st, int *N, int *s, int *levels);
 /* The power-iteration estimate mu of the largest eigenvalue of D^{-1}(M + dt*a_ii*K) on
  * multigrid level `level` (0 = finest) for stage `stage`; *mu = 0 on the coarsest level. */
 int irk_stepper_mu(const irk_stepper *st, int stage, int level, double *mu);
+
+/* Monolithic cycle (IRK_PC_MONOLITHIC steppers only): *levels (may be NULL) receives its level
+ * count and *mu (may be NULL) the power-iteration estimate for the Chebyshev interval on level
+ * `level` (0 = finest; 0 on the coarsest) of the forward (transpose = 0) or transposed system. */
+int irk_stepper_mmg_mu(const irk_stepper *st, int transpose, int level, double *mu, int *levels);
 
 /* Measurement hook. While enabled, every launch of kernel `family` on a full stage
  * block is bracketed by HIP events recorded on the stream it is launched on, and its

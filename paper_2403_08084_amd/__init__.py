@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libirk.so")
 
 IRK_OK, IRK_EINVAL, IRK_ENOMEM, IRK_EHIP, IRK_ENOCONV, IRK_EBREAKDOWN = 0, -1, -2, -3, -4, -5
-PC_JACOBI, PC_GS_LOWER, PC_RANA_LD, PC_GS_UPPER = 0, 1, 2, 3
+PC_JACOBI, PC_GS_LOWER, PC_RANA_LD, PC_GS_UPPER, PC_MONOLITHIC = 0, 1, 2, 3, 4
 SPLIT_AI, SPLIT_IA = 0, 1
 STAGE_COUPLED, STAGE_DIRK = 0, 1
 F64, F32, BF16 = 0, 1, 2
@@ -91,7 +91,7 @@ SYMBOLS = [
     "irk_last_error", "irk_options_default", "irk_problem_create", "irk_problem_destroy", "irk_apply_mass",
     "irk_apply_stiffness", "irk_stepper_create", "irk_stepper_destroy", "irk_stage_rhs", "irk_apply_stage_operator",
     "irk_apply_preconditioner", "irk_vcycle", "irk_solve_stages", "irk_advance", "irk_adjoint",
-    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_kernel_timer", "irk_kernel_timer_read",
+    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_read",
 ]
 
 
@@ -128,6 +128,7 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int)]
     L.irk_stepper_sizes.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ip)]
     L.irk_stepper_mu.argtypes = [vp, ip, ip, dp]
+    L.irk_stepper_mmg_mu.argtypes = [vp, ip, ip, dp, ctypes.POINTER(ip)]
     L.irk_kernel_timer.argtypes = [vp, ip, ip]
     L.irk_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ip), dp, dp]
     for name in SYMBOLS:
@@ -252,6 +253,18 @@ class Stepper:
     def mu(self, stage: int, level: int) -> float:
         v = ctypes.c_double()
         _check(lib().irk_stepper_mu(self._h, stage, level, ctypes.byref(v)))
+        return v.value
+
+    @property
+    def mmg_levels(self) -> int:
+        """Level count of the monolithic cycle (monolithic-multigrid steppers only)."""
+        L = ctypes.c_int()
+        _check(lib().irk_stepper_mmg_mu(self._h, 0, 0, None, ctypes.byref(L)))
+        return L.value
+
+    def mmg_mu(self, level: int, transpose: bool = False) -> float:
+        v = ctypes.c_double()
+        _check(lib().irk_stepper_mmg_mu(self._h, int(bool(transpose)), level, ctypes.byref(v), None))
         return v.value
 
     def kernel_timer(self, family: int = 0, enable: bool = True):

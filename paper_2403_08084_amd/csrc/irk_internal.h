@@ -22,6 +22,7 @@ constexpr int kMaxStages = 8;
 constexpr int kMaxDeg = 3;
 constexpr int kMaxRestart = 64;
 constexpr int kMaxCoarse = 1024;  // unknowns of the dense coarsest-level solve
+constexpr int kMMGMax = 4;        // stages supported by the monolithic multigrid cycle
 
 struct bf16 {
   uint16_t u;
@@ -60,6 +61,20 @@ struct MGCoef {
   int deg;
 };
 
+// One level of the monolithic cycle (Section 3.3): operator cm (x) M + dt ck (x) K on s planes,
+// additive Schwarz patch blocks cm M_vv + dt ck K_vv, Chebyshev coefficients as in MGCoef.
+struct MMGCoef {
+  int s;
+  int deg;
+  double m;   // h^2 / 36 of the level
+  double dt;
+  double c0;
+  double beta[kMaxDeg];
+  double gam[kMaxDeg];
+  double cm[kMMGMax * kMMGMax];  // row-major, row stride kMMGMax
+  double ck[kMMGMax * kMMGMax];
+};
+
 // ---------------------------------------------------------------- layout (k_stencil.hip)
 void launch_pack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st);
 void launch_unpack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st);
@@ -95,7 +110,8 @@ void launch_kappa_grad(double* grad, const double* u, const double* k, const dou
 // power iteration helpers (FP64, setup): mode 0: y = B x, 1: y = D^{-1} B x, 2: y = D x
 void launch_level_apply(const double* x, double* y, const double* kappa, Geom g, double alpha, int mode,
                         hipStream_t st);
-void launch_start_vector(double* x, Geom g, int level, hipStream_t st);
+// SplitMix64 start vector on the interior nodes; the value index is the compact node index + offset
+void launch_start_vector(double* x, Geom g, int level, hipStream_t st, uint64_t offset = 0);
 void launch_scale(double* x, long n, const double* inv_norm2_src, hipStream_t st);
 
 // ---------------------------------------------------------------- multigrid (k_mg.hip)
@@ -121,6 +137,25 @@ void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale,
                   const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
 // coarsest level: out = Binv * t on the interior nodes
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
+                      hipStream_t st);
+
+// ---------------------------------------------------------------- monolithic multigrid (k_mmg.hip)
+// prec as above; t_f64 / out_f64: t or out is an FP64 Krylov vector (s planes) instead of level storage.
+// One Chebyshev step (step 0: out = xc + c0 C^{-1}(ts t - Acal xc), xc may be null = 0; step k >= 1:
+// out = xc + beta_k (xc - xp) + gam_k C^{-1}(ts t - Acal xc), xp may be null = 0 and may alias out).
+void launch_mmg_step(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, const void* xc,
+                     const void* xp, void* out, const void* kap, Geom g, const MMGCoef& c, int step, hipStream_t st);
+// r = ts t - Acal x (level storage)
+void launch_mmg_residual(int prec, bool t_f64, const void* t, const double* tscale, const void* x, void* r,
+                         const void* kap, Geom g, const MMGCoef& c, hipStream_t st);
+// coarse t = (I (x) P^T) r;  fine x += (I (x) P) e
+void launch_mmg_restrict(int prec, const void* r, void* tc, Geom g, Geom gc, int s, hipStream_t st);
+void launch_mmg_prolong(int prec, const void* e, void* x, Geom g, Geom gc, int s, hipStream_t st);
+// coarsest level: out = Cinv (ts t) over the s (N-1)^2 stage-major unknowns (<= kMaxCoarse)
+void launch_mmg_coarse(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, void* out,
+                       const void* Cinv, Geom g, int s, hipStream_t st);
+// FP64 set-up: mode 0 out = C^{-1} Acal x, 1 out = Acal x, 2 out = C x
+void launch_mmg_apply(const double* x, double* out, const double* kap, Geom g, const MMGCoef& c, int mode,
                       hipStream_t st);
 
 // ---------------------------------------------------------------- Krylov (k_krylov.hip)

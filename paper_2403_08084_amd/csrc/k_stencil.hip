@@ -316,10 +316,11 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(BX* BY) void start_vector_kernel(double* __restrict__ x, Geom g, int level) {
+__global__ __launch_bounds__(BX* BY) void start_vector_kernel(double* __restrict__ x, Geom g, int level,
+                                                              uint64_t offset) {
   int i, j;
   if (!node_of_thread(g, i, j)) return;
-  const uint64_t dof = (uint64_t)(j - 1) * (uint64_t)(g.N - 1) + (uint64_t)(i - 1);
+  const uint64_t dof = (uint64_t)(j - 1) * (uint64_t)(g.N - 1) + (uint64_t)(i - 1) + offset;
   const uint64_t r = splitmix64(dof + ((uint64_t)level << 32));
   x[(long)j * g.pitch + i] = 2.0 * ((double)(r >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
 }
@@ -414,8 +415,8 @@ void launch_level_apply(const double* x, double* y, const double* kappa, Geom g,
                         hipStream_t st) {
   level_apply_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, y, kappa, g, alpha, mode);
 }
-void launch_start_vector(double* x, Geom g, int level, hipStream_t st) {
-  start_vector_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, g, level);
+void launch_start_vector(double* x, Geom g, int level, hipStream_t st, uint64_t offset) {
+  start_vector_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, g, level, offset);
 }
 void launch_scale(double* x, long n, const double* nrm2, hipStream_t st) {
   scale_kernel<<<flat_blocks(n), 256, 0, st>>>(x, n, nrm2);

@@ -79,6 +79,8 @@ struct Level {
   void* t = nullptr;        // right-hand side (levels >= 1)
   void* x = nullptr;        // pre-smoothed iterate (levels < L-1)
   void* e = nullptr;        // level result / coarse correction (levels >= 1)
+  void* xb = nullptr;       // monolithic cycle: second iterate buffer (levels < L-1)
+  void* r = nullptr;        // monolithic cycle: residual (levels < L-1)
   bool own64 = false;
 };
 
@@ -108,6 +110,12 @@ struct irk_stepper {
   std::vector<MGCoef> coef;   // [stage * L + level]
   std::vector<double> mu;     // [stage * L + level]
   std::vector<void*> binv;    // per stage, coarsest-level inverse in the compute type
+  // monolithic multigrid (IRK_PC_MONOLITHIC): levels with s-plane buffers, per-level coefficients and the
+  // dense inverse of the coarsest coupled operator, for the forward [0] and transposed [1] systems
+  std::vector<Level> ml;
+  std::vector<MMGCoef> mcoef[2];
+  std::vector<double> mmu[2];
+  void* mcinv[2] = {nullptr, nullptr};
   // Krylov workspace
   double* V = nullptr;    // (m+1) vectors
   double* Z = nullptr;    // m vectors
@@ -476,6 +484,257 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
   return IRK_OK;
 }
 
+// ------------------------------------------------------------------ monolithic multigrid setup
+
+// dense inverse of a general n x n row-major matrix (Gauss-Jordan with partial pivoting)
+int dense_inverse(std::vector<double>& W, int n, std::vector<double>& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int pr = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(W[(size_t)i * n + k]) > std::fabs(W[(size_t)pr * n + k])) pr = i;
+    if (!(std::fabs(W[(size_t)pr * n + k]) > 0)) return fail(IRK_EINVAL, "singular coarsest coupled operator");
+    if (pr != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(W[(size_t)k * n + j], W[(size_t)pr * n + j]);
+        std::swap(inv[(size_t)k * n + j], inv[(size_t)pr * n + j]);
+      }
+    const double d = 1.0 / W[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) {
+      W[(size_t)k * n + j] *= d;
+      inv[(size_t)k * n + j] *= d;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = W[(size_t)i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        W[(size_t)i * n + j] -= f * W[(size_t)k * n + j];
+        inv[(size_t)i * n + j] -= f * inv[(size_t)k * n + j];
+      }
+    }
+  }
+  return IRK_OK;
+}
+
+// the level operator's stage mixing: AI (I, Op), IA (Op, I), with Op = A, A^T or A^{-1}, A^{-T}
+void mmg_mixing(const irk_stepper* st, int trans, MMGCoef& c) {
+  const int s = st->s;
+  for (int q = 0; q < s; ++q)
+    for (int r = 0; r < s; ++r) {
+      const double op = st->Op[trans][q * s + r], id = (q == r) ? 1.0 : 0.0;
+      c.cm[q * kMMGMax + r] = st->ia ? op : id;
+      c.ck[q * kMMGMax + r] = st->ia ? id : op;
+    }
+}
+
+// Levels, Chebyshev coefficients (power iteration on C^{-1} Acal per level, both systems) and the coarsest
+// inverse of the monolithic cycle.
+int setup_mmg(irk_stepper* st, hipStream_t s) {
+  const irk_problem* p = st->prob;
+  const int ns = st->s;
+  std::vector<int> sizes{p->N};
+  while (sizes.back() % 2 == 0 &&
+         (sizes.back() > st->opt.mg_coarse_n || (long)ns * (sizes.back() - 1) * (sizes.back() - 1) > kMaxCoarse))
+    sizes.push_back(sizes.back() / 2);
+  const int Nc = sizes.back();
+  if ((long)ns * (Nc - 1) * (Nc - 1) > kMaxCoarse)
+    return fail(IRK_EINVAL, "monolithic multigrid needs N = Nc * 2^L with s (Nc-1)^2 <= 1024");
+  const int L = (int)sizes.size();
+  const size_t tsz = storage_bytes(st->prec);
+  st->ml.resize(L);
+  for (int l = 0; l < L; ++l) {
+    Level& lev = st->ml[l];
+    lev.g = make_geom(sizes[l]);
+    const long kcount = (long)lev.g.N * lev.g.pitch;
+    if (l == 0) {
+      lev.kap64 = p->kappa;
+    } else {
+      CHK(dev_alloc((void**)&lev.kap64, kcount * sizeof(double)));
+      lev.own64 = true;
+      launch_coarsen_kappa(st->ml[l - 1].kap64, lev.kap64, st->ml[l - 1].g, lev.g, s);
+    }
+    if (st->prec == 0) {
+      lev.kapc = lev.kap64;
+    } else {
+      CHK(dev_alloc(&lev.kapc, kcount * sizeof(float)));
+      launch_cast_f32(lev.kap64, (float*)lev.kapc, kcount, s);
+    }
+    const size_t pb = (size_t)ns * lev.g.plane * tsz;
+    auto zalloc = [&](void** q) -> int {
+      CHK(dev_alloc(q, pb));
+      HIPCHK(hipMemsetAsync(*q, 0, pb, s));
+      return IRK_OK;
+    };
+    if (l >= 1) {
+      CHK(zalloc(&lev.t));
+      CHK(zalloc(&lev.e));
+    }
+    if (l < L - 1) {
+      CHK(zalloc(&lev.x));
+      CHK(zalloc(&lev.xb));
+      CHK(zalloc(&lev.r));
+    }
+  }
+  CHK(check_launch());
+  // FP64 power iterations in Krylov workspace (cleared again afterwards)
+  double* x = st->V;
+  double* y = st->V + st->vlen;
+  double* z = st->Z;
+  for (int tr = 0; tr < 2; ++tr) {
+    st->mcoef[tr].assign(L, MMGCoef{});
+    st->mmu[tr].assign(L, 0.0);
+    for (int l = 0; l < L; ++l) {
+      MMGCoef& c = st->mcoef[tr][l];
+      c.s = ns;
+      c.deg = st->opt.cheb_degree;
+      c.m = st->ml[l].g.h * st->ml[l].g.h / 36.0;
+      c.dt = st->dt;
+      mmg_mixing(st, tr, c);
+      if (l == L - 1) continue;
+      const Geom& g = st->ml[l].g;
+      const long len = (long)ns * g.plane;
+      const long nl = (long)(g.N - 1) * (g.N - 1);
+      HIPCHK(hipMemsetAsync(x, 0, len * sizeof(double), s));
+      HIPCHK(hipMemsetAsync(y, 0, len * sizeof(double), s));
+      HIPCHK(hipMemsetAsync(z, 0, len * sizeof(double), s));
+      for (int q = 0; q < ns; ++q) launch_start_vector(x + q * g.plane, g, l, s, (uint64_t)(q * nl));
+      double* r = res_slot(st, 0);
+      double* xx = x;
+      double* yy = y;
+      for (int it = 0; it < st->opt.power_its; ++it) {
+        launch_mmg_apply(xx, yy, st->ml[l].kap64, g, c, 0, s);
+        CHK(norm2(st, yy, len, r, nullptr, s));
+        launch_scale(yy, len, r, s);
+        std::swap(xx, yy);
+      }
+      launch_mmg_apply(xx, yy, st->ml[l].kap64, g, c, 1, s);  // Acal x
+      launch_mmg_apply(xx, z, st->ml[l].kap64, g, c, 2, s);   // C x
+      CHK(dot(st, xx, yy, len, res_slot(st, 1), s));
+      CHK(dot(st, xx, z, len, res_slot(st, 2), s));
+      CHK(check_launch());
+      double h[2];
+      HIPCHK(hipMemcpyAsync(&h[0], res_slot(st, 1), sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&h[1], res_slot(st, 2), sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const double mu = h[0] / h[1];
+      if (!(std::isfinite(mu) && mu > 0)) return fail(IRK_EINVAL, "monolithic power iteration produced mu <= 0");
+      st->mmu[tr][l] = mu;
+      MGCoef cc{};
+      cheb_coef(mu, st->opt, cc);
+      c.c0 = cc.c0;
+      for (int k = 0; k < kMaxDeg; ++k) {
+        c.beta[k] = cc.beta[k];
+        c.gam[k] = cc.gam[k];
+      }
+    }
+  }
+  HIPCHK(hipMemsetAsync(st->V, 0, st->vlen * sizeof(double) * (st->opt.restart + 1), s));
+  HIPCHK(hipMemsetAsync(st->Z, 0, st->vlen * sizeof(double) * st->opt.restart, s));
+  // coarsest coupled operator cm (x) M + dt ck (x) K, its inverse, and the transposed system's (the transpose)
+  const Level& lc = st->ml[L - 1];
+  const int N = lc.g.N, m = N - 1, nc = m * m, n = ns * nc;
+  std::vector<double> kpad((size_t)N * lc.g.pitch);
+  HIPCHK(hipMemcpyAsync(kpad.data(), lc.kap64, kpad.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> Mc((size_t)nc * nc, 0.0), Kc((size_t)nc * nc, 0.0);
+  {
+    const double h = 1.0 / N;
+    const double Kr[4][4] = {{4, -1, -2, -1}, {-1, 4, -1, -2}, {-2, -1, 4, -1}, {-1, -2, -1, 4}};
+    const double Mr[4][4] = {{4, 2, 1, 2}, {2, 4, 2, 1}, {1, 2, 4, 2}, {2, 1, 2, 4}};
+    const int dx[4] = {0, 1, 1, 0}, dy[4] = {0, 0, 1, 1};
+    for (int ey = 0; ey < N; ++ey)
+      for (int ex = 0; ex < N; ++ex) {
+        int idx[4];
+        for (int a = 0; a < 4; ++a) {
+          const int i = ex + dx[a], j = ey + dy[a];
+          idx[a] = (i >= 1 && i <= m && j >= 1 && j <= m) ? (j - 1) * m + (i - 1) : -1;
+        }
+        const double ke = kpad[(size_t)ey * lc.g.pitch + ex];
+        for (int a = 0; a < 4; ++a)
+          for (int c = 0; c < 4; ++c)
+            if (idx[a] >= 0 && idx[c] >= 0) {
+              Kc[(size_t)idx[a] * nc + idx[c]] += ke * Kr[a][c] / 6.0;
+              Mc[(size_t)idx[a] * nc + idx[c]] += h * h * Mr[a][c] / 36.0;
+            }
+      }
+  }
+  const MMGCoef& c0 = st->mcoef[0][L - 1];
+  std::vector<double> W((size_t)n * n, 0.0), inv;
+  for (int q = 0; q < ns; ++q)
+    for (int r = 0; r < ns; ++r) {
+      const double a = c0.cm[q * kMMGMax + r], b = st->dt * c0.ck[q * kMMGMax + r];
+      if (a == 0.0 && b == 0.0) continue;
+      for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j)
+          W[(size_t)(q * nc + i) * n + r * nc + j] = a * Mc[(size_t)i * nc + j] + b * Kc[(size_t)i * nc + j];
+    }
+  CHK(dense_inverse(W, n, inv));
+  for (int tr = 0; tr < 2; ++tr) {
+    std::vector<double> use(inv.size());
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) use[(size_t)i * n + j] = tr ? inv[(size_t)j * n + i] : inv[(size_t)i * n + j];
+    if (st->prec == 0) {
+      CHK(dev_alloc(&st->mcinv[tr], use.size() * sizeof(double)));
+      HIPCHK(hipMemcpy(st->mcinv[tr], use.data(), use.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(use.begin(), use.end());
+      CHK(dev_alloc(&st->mcinv[tr], f.size() * sizeof(float)));
+      HIPCHK(hipMemcpy(st->mcinv[tr], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+  }
+  return IRK_OK;
+}
+
+// out = one monolithic V-cycle for the coupled system (forward or transposed) applied to tscale * t
+// (FP64 padded stage blocks)
+int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, double* out, bool trans, hipStream_t s) {
+  std::vector<Level>& ml = st->ml;
+  const int L = (int)ml.size();
+  const int pr = st->prec, ns = st->s;
+  const MMGCoef* cf = st->mcoef[trans ? 1 : 0].data();
+  const void* cinv = st->mcinv[trans ? 1 : 0];
+  if (L == 1) {
+    launch_mmg_coarse(pr, true, true, t, tscale, out, cinv, ml[0].g, ns, s);
+    return check_launch();
+  }
+  std::vector<void*> xl(L, nullptr);
+  for (int l = 0; l < L - 1; ++l) {
+    const bool f64 = l == 0;
+    const void* tl = f64 ? (const void*)t : ml[l].t;
+    const double* ts = f64 ? tscale : nullptr;
+    void* cur = nullptr;
+    void* prev = nullptr;
+    for (int k = 0; k < cf[l].deg; ++k) {
+      void* o = (cur == ml[l].x) ? ml[l].xb : ml[l].x;
+      launch_mmg_step(pr, f64, false, tl, ts, cur, prev, o, ml[l].kapc, ml[l].g, cf[l], k, s);
+      prev = cur;
+      cur = o;
+    }
+    xl[l] = cur;
+    launch_mmg_residual(pr, f64, tl, ts, cur, ml[l].r, ml[l].kapc, ml[l].g, cf[l], s);
+    launch_mmg_restrict(pr, ml[l].r, ml[l + 1].t, ml[l].g, ml[l + 1].g, ns, s);
+  }
+  launch_mmg_coarse(pr, false, false, ml[L - 1].t, nullptr, ml[L - 1].e, cinv, ml[L - 1].g, ns, s);
+  for (int l = L - 2; l >= 0; --l) {
+    const bool f64 = l == 0;
+    const void* tl = f64 ? (const void*)t : ml[l].t;
+    const double* ts = f64 ? tscale : nullptr;
+    void* cur = xl[l];
+    launch_mmg_prolong(pr, ml[l + 1].e, cur, ml[l].g, ml[l + 1].g, ns, s);
+    void* prev = nullptr;
+    for (int k = 0; k < cf[l].deg; ++k) {
+      const bool last = k + 1 == cf[l].deg;
+      void* o = last ? (f64 ? (void*)out : ml[l].e) : ((cur == ml[l].x) ? ml[l].xb : ml[l].x);
+      launch_mmg_step(pr, f64, last && f64, tl, ts, cur, prev, o, ml[l].kapc, ml[l].g, cf[l], k, s);
+      prev = cur;
+      cur = o;
+    }
+  }
+  return check_launch();
+}
+
 // ------------------------------------------------------------------ preconditioner
 
 // out = one V-cycle for block `stage` applied to tscale * t (FP64 padded planes)
@@ -509,6 +768,7 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
 // C = Atil^{-1}, B_i = M + dt atil_ii K (one V-cycle is linear, so atil_ii scales its input).
 int precondition(irk_stepper* st, const double* v, const double* vscale, double* z, bool trans, hipStream_t s) {
   if (st->sys >= 0) return vcycle(st, st->sys, v, vscale, z, s);  // one DIRK stage: one V-cycle
+  if (st->opt.precond == IRK_PC_MONOLITHIC) return mmg_vcycle(st, v, vscale, z, trans, s);
   const long plane = st->g.plane;
   const int ns = st->s;
   const Coefs a = ptil_of(st, trans);
@@ -1032,6 +1292,18 @@ void irk_stepper_destroy(irk_stepper* st) {
     dev_free(L.e);
   }
   for (void* p : st->binv) dev_free(p);
+  for (size_t l = 0; l < st->ml.size(); ++l) {
+    Level& L = st->ml[l];
+    if (L.kapc && L.kapc != L.kap64) dev_free(L.kapc);
+    if (L.own64) dev_free(L.kap64);
+    dev_free(L.t);
+    dev_free(L.x);
+    dev_free(L.xb);
+    dev_free(L.r);
+    dev_free(L.e);
+  }
+  dev_free(st->mcinv[0]);
+  dev_free(st->mcinv[1]);
   dev_free(st->V);
   dev_free(st->Z);
   dev_free(st->f);
@@ -1065,7 +1337,9 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   irk_options o;
   irk_options_default(&o);
   if (opts) o = *opts;
-  if (o.precond < IRK_PC_JACOBI || o.precond > IRK_PC_GS_UPPER) return fail(IRK_EINVAL, "unknown precond");
+  if (o.precond < IRK_PC_JACOBI || o.precond > IRK_PC_MONOLITHIC) return fail(IRK_EINVAL, "unknown precond");
+  if (o.precond == IRK_PC_MONOLITHIC && tab->s > kMMGMax)
+    return fail(IRK_EINVAL, "the monolithic multigrid cycle supports up to 4 stages");
   if (o.restart < 1 || o.restart > 32) return fail(IRK_EINVAL, "restart must be in 1..32");
   if (o.max_it < 1) return fail(IRK_EINVAL, "max_it must be >= 1");
   if (!(o.rtol > 0) || !(o.rtol < 1)) return fail(IRK_EINVAL, "rtol must be in (0, 1)");
@@ -1130,7 +1404,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
     for (int i = 0; i < s; ++i)
       for (int j = 0; j < s; ++j) {
         double f = 0, t = 0;
-        if (o.precond == IRK_PC_JACOBI) {
+        if (o.precond == IRK_PC_JACOBI || o.precond == IRK_PC_MONOLITHIC) {
           f = t = (i == j) ? tab->A[i * s + i] : 0.0;
         } else if (o.precond == IRK_PC_GS_LOWER) {
           f = (j <= i) ? tab->A[i * s + j] : 0.0;
@@ -1210,6 +1484,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   if (rc == IRK_OK && hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess)
     rc = fail(IRK_EHIP, "stream creation failed");
   if (rc == IRK_OK) rc = setup_multigrid(st, hs);
+  if (rc == IRK_OK && o.precond == IRK_PC_MONOLITHIC) rc = setup_mmg(st, hs);
   if (rc == IRK_OK && hipStreamSynchronize(hs) != hipSuccess) rc = fail(IRK_EHIP, "setup synchronisation failed");
   if (rc != IRK_OK) {
     std::string keep = g_err;
@@ -1234,6 +1509,18 @@ int irk_stepper_mu(const irk_stepper* st, int stage, int level, double* mu) {
   const int L = (int)st->lv.size();
   if (stage < 0 || stage >= st->s || level < 0 || level >= L || !mu) return fail(IRK_EINVAL, "bad stage/level");
   *mu = st->mu[(size_t)stage * L + level];
+  return IRK_OK;
+}
+
+int irk_stepper_mmg_mu(const irk_stepper* st, int transpose, int level, double* mu, int* levels) {
+  CHK(validate_stepper(st));
+  if (st->opt.precond != IRK_PC_MONOLITHIC) return fail(IRK_EINVAL, "not a monolithic-multigrid stepper");
+  const int L = (int)st->ml.size();
+  if (levels) *levels = L;
+  if (mu) {
+    if (level < 0 || level >= L) return fail(IRK_EINVAL, "bad level");
+    *mu = st->mmu[transpose ? 1 : 0][level];
+  }
   return IRK_OK;
 }
 

@@ -20,7 +20,8 @@ def _setup(N, nsteps, dt):
 
 @pytest.mark.parametrize("nsnap,split,pc", [(2, P.SPLIT_AI, P.PC_GS_LOWER), (3, P.SPLIT_AI, P.PC_GS_LOWER),
                                             (100, P.SPLIT_AI, P.PC_GS_LOWER), (3, P.SPLIT_AI, P.PC_RANA_LD),
-                                            (3, P.SPLIT_IA, P.PC_GS_LOWER), (3, P.SPLIT_IA, P.PC_RANA_LD)])
+                                            (3, P.SPLIT_IA, P.PC_GS_LOWER), (3, P.SPLIT_IA, P.PC_RANA_LD),
+                                            (3, P.SPLIT_AI, P.PC_MONOLITHIC)])
 def test_adjoint_matches_oracle(nsnap, split, pc):
     # the gradient of the discrete step map does not depend on the stage formulation or the preconditioner
     N, nsteps, dt = 32, 6, 1e-3

@@ -1,0 +1,112 @@
+"""GPU parity: the monolithic multigrid cycle (Section 3.3) vs the oracle's CSR statement (oracle.mmg), and the
+FGMRES solves and time steps it preconditions."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fem, mmg, step
+from oracle import tableaux as OT
+import paper_2403_08084_amd as P
+import synth
+from gpu_util import dev, host, make, rel
+
+pytestmark = pytest.mark.gpu
+
+_TABS = {"radau1": (lambda: OT.radau_iia(1), lambda: P.tableaux.radau_iia(1)),
+         "radau2": (lambda: OT.radau_iia(2), lambda: P.tableaux.radau_iia(2)),
+         "radau3": (lambda: OT.radau_iia(3), lambda: P.tableaux.radau_iia(3)),
+         "gl4": (lambda: OT.gauss_legendre(4), lambda: P.tableaux.gauss_legendre(4))}
+_SPLIT = {"AI": P.SPLIT_AI, "IA": P.SPLIT_IA}
+
+
+@pytest.mark.parametrize("tname,N,splitting", [("radau3", 64, "AI"), ("radau3", 96, "IA"), ("gl4", 64, "AI"),
+                                               ("radau2", 128, "AI"), ("radau1", 33, "AI"), ("gl4", 32, "IA")])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_mmg_vcycle_matches_oracle(tname, N, splitting, transpose):
+    dt = 1e-3
+    kap = synth.grf_kappa(N, 3)
+    otab, ptab = _TABS[tname][0](), _TABS[tname][1]()
+    s = otab["A"].shape[0]
+    H = mmg.MonolithicHierarchy(N, kap, dt, *mmg.mixing(otab["A"], splitting, transpose))
+    _, stp = make(N, kap, ptab, dt, precond=P.PC_MONOLITHIC, splitting=_SPLIT[splitting])
+    assert stp.mmg_levels == len(H.sizes)
+    for l in range(len(H.sizes) - 1):
+        assert abs(stp.mmg_mu(l, transpose) - H.mus[l]) <= 1e-11 * H.mus[l]
+    v = synth.random_stage_block(N, s, 14).ravel()
+    z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
+    assert rel(z, H.vcycle(v)) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(P.F32, 2e-5), (P.BF16, 3e-2)])
+def test_mmg_reduced_precision(prec, tol):
+    N, dt = 128, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    A = OT.radau_iia(3)["A"]
+    H = mmg.MonolithicHierarchy(N, kap, dt, *mmg.mixing(A))
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=P.PC_MONOLITHIC, mg_precision=prec)
+    v = synth.random_stage_block(N, 3, 15).ravel()
+    assert rel(host(stp.apply_preconditioner(dev(v))), H.vcycle(v)) < tol
+
+
+@pytest.mark.parametrize("splitting", ["AI", "IA"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_mmg_solve_stages_matches_direct(splitting, transpose):
+    N, dt = 64, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    A = OT.radau_iia(3)["A"]
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=P.PC_MONOLITHIC, rtol=1e-12,
+                  splitting=_SPLIT[splitting])
+    f = synth.random_stage_block(N, 3, 24).ravel()
+    x, stats = stp.solve_stages(dev(f), transpose=transpose)
+    Acal = step.coupled_matrix(M, K, A, dt) if splitting == "AI" else step.coupled_matrix_ia(M, K, A, dt)
+    if transpose:
+        Acal = Acal.T.tocsc()
+    ref = spla.spsolve(Acal, f)
+    assert stats["last_rel_resid"] <= 1e-12
+    assert rel(host(x), ref) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [(P.F64, 1e-10), (P.F32, 1e-8)])
+def test_mmg_advance_matches_oracle(prec, tol):
+    # Gauss-Legendre(4), variable kappa, dt = 5e-4 (the shape of the GL4 workload) at 128^2
+    N, dt, nsteps = 128, 5e-4, 4
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    _, stp = make(N, kap, P.tableaux.gauss_legendre(4), dt, precond=P.PC_MONOLITHIC, rtol=1e-12, mg_precision=prec)
+    u = dev(u0)
+    gpu = []
+    for _ in range(nsteps):
+        stp.advance(u, 1)
+        gpu.append(host(u))
+    ora = step.run(N, kap, OT.gauss_legendre(4), dt, nsteps, u0)[1:]
+    assert max(rel(a, b) for a, b in zip(gpu, ora)) < tol
+
+
+def test_mmg_iterations_nearly_flat_in_stages():
+    # Section 3.3: the monolithic cycle's convergence does not depend explicitly on the number of stages
+    N, dt = 128, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    its = {}
+    for s in (1, 2, 3, 4):
+        _, stp = make(N, kap, P.tableaux.radau_iia(s), dt, precond=P.PC_MONOLITHIC, rtol=1e-10)
+        u = dev(u0)
+        _, st = stp.advance(u, 2)
+        its[s] = st["fgmres_its_total"] / 2
+    print(its)
+    assert its[4] <= its[1] + 4
+
+
+def test_mmg_limits():
+    N = 16
+    prob = P.Problem(N, dev(np.ones(N * N)))
+    with pytest.raises(P.IrkError) as e:
+        P.Stepper(prob, P.tableaux.radau_iia(5), 1e-3, precond=P.PC_MONOLITHIC)
+    assert e.value.code == P.IRK_EINVAL
+    prob33 = P.Problem(33, dev(np.ones(33 * 33)))
+    with pytest.raises(P.IrkError):  # odd N: 3 * 32^2 unknowns cannot be coarsened below 1024
+        P.Stepper(prob33, P.tableaux.radau_iia(3), 1e-3, precond=P.PC_MONOLITHIC)
+    _, stp = make(N, np.ones(N * N), P.tableaux.radau_iia(3), 1e-3)
+    with pytest.raises(P.IrkError):
+        stp.mmg_levels
