@@ -16,8 +16,10 @@ oracle's full-size result (tests/golden).
 Metric: DoF-stage-steps/s = n * s * steps / time, inputs resident in HBM.
 Extra JSON objects: "roofline" (the streaming Gram-Schmidt pass, timed with HIP
 events on its launch stream by the library's measurement hook, algorithmic
-bytes vs the 8 TB/s HBM3E peak) and "cpu_baseline" (the CPU oracle on a bounded
-sample of the same workload).
+bytes vs the 8 TB/s HBM3E peak), "cpu_baseline" (the CPU oracle on a bounded
+sample of the same workload) and "variants" (the same workload, mixed form,
+solved with the Rana-LD preconditioner in the IA form and with the monolithic
+multigrid cycle).
 """
 from __future__ import annotations
 
@@ -61,6 +63,8 @@ def parse():
     ap.add_argument("--guess", choices=["zero", "prev"], default="zero")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--coarse-n", type=int, default=32)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the extra mixed-precision runs of the same workload with the other preconditioners")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (counter calibration for profiles)")
     return ap.parse_args()
@@ -242,6 +246,18 @@ def main():
                        "error_vs_oracle": golden_error(u64h, args.steps, args.tableau)}
         out["mixed_over_fp64"] = value / out["fp64"]["value"]
         out["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(uh - u64h) / np.linalg.norm(u64h))
+    if not args.no_variants and args.tableau == "radau3" and args.stage_type == "coupled":
+        # the same workload and accuracy target solved with the other stage preconditioners (mixed form)
+        out["variants"] = {}
+        for name, extra in (("P_LD, IA splitting", dict(precond=P.PC_RANA_LD, splitting=P.SPLIT_IA)),
+                            ("monolithic MG", dict(precond=P.PC_MONOLITHIC, splitting=P.SPLIT_AI))):
+            o2 = dict(opts)
+            o2.update(extra)
+            _, uv, msv, stv, _ = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, prec, o2)
+            out["variants"][name] = {"value": n * s * args.steps / (msv / 1e3), "ms_per_step": msv / args.steps,
+                                     "fgmres_its_per_step": stv["fgmres_its_total"] / max(1, args.steps),
+                                     "error_vs_oracle": golden_error(uv.cpu().numpy(), args.steps, args.tableau)}
+            del uv
     if not args.no_roofline:
         # same steps again with the measurement hook on the Gram-Schmidt pass (launched eagerly)
         stp.kernel_timer(0, True)
