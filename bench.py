@@ -14,7 +14,7 @@ the same run and reported beside it, and both are checked against the CPU
 oracle's full-size result (tests/golden).
 
 Metric: DoF-stage-steps/s = n * s * steps / time, inputs resident in HBM.
-Extra JSON objects: "roofline" (the streaming Gram-Schmidt pass, timed with HIP
+Extra JSON objects: "roofline" (the streaming Gram-Schmidt passes, timed with HIP
 events on its launch stream by the library's measurement hook, algorithmic
 bytes vs the 8 TB/s HBM3E peak), "cpu_baseline" (the CPU oracle on a bounded
 sample of the same workload) and "variants" (the same workload, mixed form,
@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 METRIC = "DoF-stage-steps/s at 1e-8 rel. error, RadauIIA s=3, 1024² Q1; mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "config4_radau3_1024.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "ortho_kernel_traffic.txt")
+TRAFFIC = os.path.join(ROOT, "profiles", "gram_schmidt_traffic.txt")
 KRYLOV_SRC = os.path.join(ROOT, "paper_2403_08084_amd", "csrc", "k_krylov.hip")
 
 
@@ -59,7 +59,7 @@ def parse():
                     help="one coupled stage solve, or stage-by-stage solves for a DIRK tableau")
     ap.add_argument("--splitting", choices=["ai", "ia"], default="ai",
                     help="stage formulation: eq:block_struct_AI (k) or eq:block_struct_IA (w = A k)")
-    ap.add_argument("--orth", choices=["cgs2", "selective"], default="cgs2")
+    ap.add_argument("--orth", choices=["cgs2", "selective", "dcgs2"], default="dcgs2")
     ap.add_argument("--guess", choices=["zero", "prev"], default="zero")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--coarse-n", type=int, default=32)
@@ -73,7 +73,7 @@ def parse():
 def solver_options(P, args):
     return dict(precond={"gs": P.PC_GS_LOWER, "jacobi": P.PC_JACOBI, "rana": P.PC_RANA_LD, "gsu": P.PC_GS_UPPER,
                           "mmg": P.PC_MONOLITHIC}[args.precond],
-                orth={"cgs2": P.ORTH_CGS2, "selective": P.ORTH_CGS_SELECTIVE}[args.orth],
+                orth={"cgs2": P.ORTH_CGS2, "selective": P.ORTH_CGS_SELECTIVE, "dcgs2": P.ORTH_DCGS2}[args.orth],
                 initial_guess={"zero": P.GUESS_ZERO, "prev": P.GUESS_PREV}[args.guess],
                 splitting={"ai": P.SPLIT_AI, "ia": P.SPLIT_IA}[args.splitting],
                 stage_type={"coupled": P.STAGE_COUPLED, "dirk": P.STAGE_DIRK}[args.stage_type],
@@ -128,7 +128,7 @@ def golden_error(u, steps, tableau="radau3"):
 
 
 def traffic_bytes_per_launch():
-    """Counter-measured HBM bytes per Gram-Schmidt pass from the committed profile summary.
+    """Counter-measured HBM bytes per Gram-Schmidt pass (DCGS2 reduction and update) from the committed profile.
 
     Used only if the summary was taken on the current k_krylov.hip (its sha256 prefix
     is recorded in the summary); otherwise None."""
@@ -266,10 +266,12 @@ def main():
         launches, kms, kbytes = stp.kernel_timer_read()
         stp.kernel_timer(0, False)
         achieved = kbytes / (kms / 1e3) / 1e9
-        tb = traffic_bytes_per_launch()
+        tb = traffic_bytes_per_launch() if args.orth == "dcgs2" else None
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
-                           "kernel": "ortho_kernel (streaming Gram-Schmidt pass)", "launches": launches,
+                           "kernel": ("dots2_kernel + dcgs2_update_kernel (streaming Gram-Schmidt passes)"
+                                      if args.orth == "dcgs2" else "ortho_kernel (streaming Gram-Schmidt pass)"),
+                           "launches": launches,
                            "avg_us": 1e3 * kms / max(1, launches),
                            "algorithmic_bytes_per_launch": kbytes / max(1, launches)}
     if not args.no_cpu_baseline:

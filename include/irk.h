@@ -63,7 +63,10 @@ typedef enum {
  * and one monolithic multigrid V-cycle on the whole stage-coupled system (Section 3.3) */
 enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2, IRK_PC_GS_UPPER = 3, IRK_PC_MONOLITHIC = 4 };
 enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precision */
-enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1 };    /* Gram-Schmidt variant */
+/* Gram-Schmidt variant of the Arnoldi process: classical with re-orthogonalisation (three passes per
+ * step), with selective re-orthogonalisation, or its delayed one-reduction form (two passes per step;
+ * Swirydowicz et al., Numer. Linear Algebra Appl. 2021) */
+enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1, IRK_ORTH_DCGS2 = 2 };
 enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial guess */
 /* Stage formulation (Section 2.4): AI solves eq:block_struct_AI for the stage derivatives k;
  * IA solves eq:block_struct_IA, (A^{-1} (x) M + dt I (x) K) w = f, for w = (A (x) I) k
@@ -96,7 +99,7 @@ typedef struct {
   double cheb_hi;
   int power_its;      /* power iterations for the largest eigenvalue mu            */
   int mg_precision;   /* IRK_F64, IRK_F32 or IRK_BF16 (storage; BF16 computes in FP32) */
-  int orth;           /* IRK_ORTH_CGS2 or IRK_ORTH_CGS_SELECTIVE                  */
+  int orth;           /* IRK_ORTH_DCGS2 (default), IRK_ORTH_CGS2 or IRK_ORTH_CGS_SELECTIVE */
   int initial_guess;  /* IRK_GUESS_ZERO or IRK_GUESS_PREV (previous step's k)     */
   int use_graphs;     /* 1: replay each Krylov iteration as a captured HIP graph;  
                          0: launch every kernel eagerly (same arithmetic)          */

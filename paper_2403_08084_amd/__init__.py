@@ -27,7 +27,7 @@ PC_JACOBI, PC_GS_LOWER, PC_RANA_LD, PC_GS_UPPER, PC_MONOLITHIC = 0, 1, 2, 3, 4
 SPLIT_AI, SPLIT_IA = 0, 1
 STAGE_COUPLED, STAGE_DIRK = 0, 1
 F64, F32, BF16 = 0, 1, 2
-ORTH_CGS2, ORTH_CGS_SELECTIVE = 0, 1
+ORTH_CGS2, ORTH_CGS_SELECTIVE, ORTH_DCGS2 = 0, 1, 2
 GUESS_ZERO, GUESS_PREV = 0, 1
 
 _STATUS = {IRK_EINVAL: "EINVAL", IRK_ENOMEM: "ENOMEM", IRK_EHIP: "EHIP", IRK_ENOCONV: "ENOCONV",

@@ -73,6 +73,13 @@ struct MMGCoef {
   double gam[kMaxDeg];
   double cm[kMMGMax * kMMGMax];  // row-major, row stride kMMGMax
   double ck[kMMGMax * kMMGMax];
+  // patch blocks in closed form: C_v = (1/w) (I + tau B) with B the non-identity mixing matrix,
+  // AI: tau = tfac * K_vv, w = wfac; IA: tau = tfac / K_vv, w = wfac / K_vv; then
+  // C_v^{-1} = w adj(I + tau B) / det(I + tau B), adj = sum_k tau^k adj_k, det = sum_k tau^k det_k
+  int ia;
+  double tfac, wfac;
+  double adj[kMMGMax * kMMGMax * kMMGMax];  // [k][q][r]
+  double det[kMMGMax + 1];
 };
 
 // ---------------------------------------------------------------- layout (k_stencil.hip)
@@ -140,17 +147,13 @@ void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tsc
                       hipStream_t st);
 
 // ---------------------------------------------------------------- monolithic multigrid (k_mmg.hip)
-// prec as above; t_f64 / out_f64: t or out is an FP64 Krylov vector (s planes) instead of level storage.
-// One Chebyshev step (step 0: out = xc + c0 C^{-1}(ts t - Acal xc), xc may be null = 0; step k >= 1:
-// out = xc + beta_k (xc - xp) + gam_k C^{-1}(ts t - Acal xc), xp may be null = 0 and may alias out).
-void launch_mmg_step(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, const void* xc,
-                     const void* xp, void* out, const void* kap, Geom g, const MMGCoef& c, int step, hipStream_t st);
-// r = ts t - Acal x (level storage)
-void launch_mmg_residual(int prec, bool t_f64, const void* t, const double* tscale, const void* x, void* r,
-                         const void* kap, Geom g, const MMGCoef& c, hipStream_t st);
-// coarse t = (I (x) P^T) r;  fine x += (I (x) P) e
-void launch_mmg_restrict(int prec, const void* r, void* tc, Geom g, Geom gc, int s, hipStream_t st);
-void launch_mmg_prolong(int prec, const void* e, void* x, Geom g, Geom gc, int s, hipStream_t st);
+// prec as above; t_f64 / io_f64: t (and out) is an FP64 Krylov vector (s planes) instead of level storage.
+// DOWN: Chebyshev pre-smoothing from zero of Acal x = ts t, writes x and the restricted residual tc.
+void launch_mmg_down(int prec, bool t_f64, const void* t, const double* tscale, void* x, void* tc, const void* kap,
+                     Geom g, Geom gc, const MMGCoef& c, hipStream_t st);
+// UP: x0 = x + (I (x) P) e, Chebyshev post-smoothing, writes out.
+void launch_mmg_up(int prec, bool io_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
+                   const void* kap, Geom g, Geom gc, const MMGCoef& c, hipStream_t st);
 // coarsest level: out = Cinv (ts t) over the s (N-1)^2 stage-major unknowns (<= kMaxCoarse)
 void launch_mmg_coarse(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, void* out,
                        const void* Cinv, Geom g, int s, hipStream_t st);
@@ -184,5 +187,24 @@ struct ReduceWork {
 // ev0/ev1 (optional): start/stop events of the streaming pass's own dispatch on st (not the finish)
 void launch_ortho(const OrthoArgs& a, const ReduceWork& w, hipStream_t st, hipEvent_t ev0 = nullptr,
                   hipEvent_t ev1 = nullptr);
+
+// Delayed CGS2 (one reduction per Arnoldi step). Q = V_0..V_{nv-1} (finished), u (previous direction),
+// w (new direction). res receives [Q^T u (nv), Q^T w (nv), u.u, u.w, w.w, beta, 1/beta, h, nu, flag].
+constexpr int kMaxDcgs2 = 31;
+constexpr int kDcgs2Res = 2 * (kMaxDcgs2 + 1) + 8;
+struct D2Args {
+  const double* V;
+  long vstride;
+  int nv;
+  double* u;
+  double* w;
+  long len;
+  double* res;
+};
+void launch_dcgs2_dots(const D2Args& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
+// u <- (u - Q a)/beta, w <- w - Q s - h u (coefficients read from res on the device)
+void launch_dcgs2_update(const D2Args& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 
 }  // namespace irk

@@ -1,4 +1,5 @@
-// Multi-vector Krylov pass for FGMRES (classical Gram-Schmidt).
+// Multi-vector Krylov passes for FGMRES: classical Gram-Schmidt with re-orthogonalisation (CGS2),
+// and its delayed one-reduction form (DCGS2).
 //
 // One pass streams a set of basis vectors V_0..V_{nv-1} and the vector w once:
 //   optionally  w <- w - sum_k c_k V_k          (projection / combination)
@@ -151,6 +152,184 @@ __global__ __launch_bounds__(NF) void finish_kernel(OrthoArgs a, ReduceWork rw, 
   }
 }
 
+// ---------------------------------------------------------------- DCGS2
+//
+// Delayed CGS2 (Swirydowicz, Langou, Ananthan, Yang and Thomas, "Low synchronization Gram-Schmidt and
+// GMRES algorithms", Numer. Linear Algebra Appl. 2021): at Arnoldi step j the new direction w and the
+// previous direction u (projected once, not yet re-orthogonalised or normalised) are treated together,
+// one reduction giving Q^T u, Q^T w, u.u, u.w, w.w; u is then re-orthogonalised and normalised into
+// q_j and w projected against Q and q_j in one streaming update pass.
+
+constexpr int NF2 = 256;  // threads of the DCGS2 finishing kernel (each sums nb / NF2 partials)
+
+template <int NV, int U>
+__device__ __forceinline__ void process2(const D2Args& a, long q0, long stride, double (&acc)[2 * NV + 3]) {
+  double uv[U], wv[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    uv[t] = a.u[q0 + t * stride];
+    wv[t] = a.w[q0 + t * stride];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const double v = a.V[k * a.vstride + q0 + t * stride];
+      acc[k] += v * uv[t];
+      acc[NV + k] += v * wv[t];
+    }
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    acc[2 * NV] += uv[t] * uv[t];
+    acc[2 * NV + 1] += uv[t] * wv[t];
+    acc[2 * NV + 2] += wv[t] * wv[t];
+  }
+}
+
+template <int NV>
+__global__ __launch_bounds__(NT) void dots2_kernel(D2Args a, ReduceWork rw) {
+  constexpr int CNT = 2 * NV + 3;
+  constexpr int U = NV <= 2 ? 4 : (NV <= 8 ? 2 : 1);
+  double acc[CNT];
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) acc[k] = 0.0;
+  const long stride = (long)gridDim.x * NT;
+  const long len = a.len;
+  long q0 = (long)blockIdx.x * NT + threadIdx.x;
+  for (; q0 + (U - 1) * stride < len; q0 += U * stride) process2<NV, U>(a, q0, stride, acc);
+  for (; q0 < len; q0 += stride) process2<NV, 1>(a, q0, stride, acc);
+  __shared__ double red[CNT * NW];
+  __shared__ double tot[CNT];
+  block_reduce<CNT>(acc, red, tot);
+  const int mb = rw.max_blocks;
+  for (int k = threadIdx.x; k < CNT; k += NT) rw.partial[(long)k * mb + blockIdx.x] = tot[k];
+}
+
+// Sums the partials in a fixed order and derives the step's coefficients:
+//   res[0..NV) = a = Q^T u, res[NV..2NV) = s = Q^T w, then u.u, u.w, w.w,
+//   beta = |u - Q a| = sqrt(u.u - |a|^2), 1/beta, h = q_j . w = (u.w - a.s) / beta,
+//   nu = w.w - |s|^2 - h^2 (the squared norm of the next direction before its re-orthogonalisation),
+//   flag (1 if beta is not a positive finite number).
+template <int NV>
+__global__ __launch_bounds__(NF2) void dcgs2_finish_kernel(D2Args a, ReduceWork rw, int nb) {
+  constexpr int CNT = 2 * NV + 3;
+  constexpr int W2 = NF2 / 64;
+  const int mb = rw.max_blocks;
+  double fin[CNT];
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) fin[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NF2)
+#pragma unroll
+    for (int k = 0; k < CNT; ++k) fin[k] += rw.partial[(long)k * mb + b];
+  __shared__ double red[CNT * W2];
+  __shared__ double tot[CNT];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < CNT; ++k) {
+    const double sm = wave_sum(fin[k]);
+    if (lane == 0) red[k * W2 + wid] = sm;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < CNT; k += NF2) {
+    double sm = 0.0;
+#pragma unroll
+    for (int w = 0; w < W2; ++w) sm += red[k * W2 + w];
+    tot[k] = sm;
+    a.res[k] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double na = 0.0, as = 0.0, ns = 0.0;
+    for (int k = 0; k < NV; ++k) {
+      na += tot[k] * tot[k];
+      as += tot[k] * tot[NV + k];
+      ns += tot[NV + k] * tot[NV + k];
+    }
+    const double b2 = tot[2 * NV] - na;
+    const bool ok = b2 > 0.0 && b2 < 1.0e300;
+    const double beta = ok ? sqrt(b2) : 0.0;
+    const double ib = ok ? 1.0 / beta : 0.0;
+    const double h = (tot[2 * NV + 1] - as) * ib;
+    a.res[CNT] = beta;
+    a.res[CNT + 1] = ib;
+    a.res[CNT + 2] = h;
+    a.res[CNT + 3] = tot[2 * NV + 2] - ns - h * h;
+    a.res[CNT + 4] = ok ? 0.0 : 1.0;
+  }
+}
+
+template <int NV, int U>
+__device__ __forceinline__ void process_upd(const D2Args& a, const double (&c1)[NV > 0 ? NV : 1],
+                                            const double (&c2)[NV > 0 ? NV : 1], double ib, double h, long q0,
+                                            long stride) {
+  double uv[U], wv[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    uv[t] = a.u[q0 + t * stride];
+    wv[t] = a.w[q0 + t * stride];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const double v = a.V[k * a.vstride + q0 + t * stride];
+      uv[t] -= c1[k] * v;
+      wv[t] -= c2[k] * v;
+    }
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const double qn = uv[t] * ib;
+    a.u[q0 + t * stride] = qn;
+    a.w[q0 + t * stride] = wv[t] - h * qn;
+  }
+}
+
+// u <- (u - Q a) / beta  (the finished q_j);  w <- w - Q s - h q_j  (the next direction)
+template <int NV>
+__global__ __launch_bounds__(NT) void dcgs2_update_kernel(D2Args a) {
+  constexpr int NVV = NV > 0 ? NV : 1;
+  constexpr int U = NV <= 2 ? 4 : (NV <= 8 ? 2 : 1);
+  constexpr int CNT = 2 * NV + 3;
+  double c1[NVV], c2[NVV];
+#pragma unroll
+  for (int k = 0; k < NVV; ++k) {
+    c1[k] = k < NV ? a.res[k] : 0.0;
+    c2[k] = k < NV ? a.res[NV + k] : 0.0;
+  }
+  const double ib = a.res[CNT + 1], h = a.res[CNT + 2];
+  const long stride = (long)gridDim.x * NT;
+  const long len = a.len;
+  long q0 = (long)blockIdx.x * NT + threadIdx.x;
+  for (; q0 + (U - 1) * stride < len; q0 += U * stride) process_upd<NV, U>(a, c1, c2, ib, h, q0, stride);
+  for (; q0 < len; q0 += stride) process_upd<NV, 1>(a, c1, c2, ib, h, q0, stride);
+}
+
+using D2Fn = void (*)(D2Args, ReduceWork);
+using D2FinFn = void (*)(D2Args, ReduceWork, int);
+using D2UpdFn = void (*)(D2Args);
+
+template <int... I>
+struct Table2 {
+  static D2Fn dots(int nv) {
+    D2Fn out = nullptr;
+    ((nv == I ? (out = dots2_kernel<I>, 0) : 0), ...);
+    return out;
+  }
+  static D2FinFn fin(int nv) {
+    D2FinFn out = nullptr;
+    ((nv == I ? (out = dcgs2_finish_kernel<I>, 0) : 0), ...);
+    return out;
+  }
+  static D2UpdFn upd(int nv) {
+    D2UpdFn out = nullptr;
+    ((nv == I ? (out = dcgs2_update_kernel<I>, 0) : 0), ...);
+    return out;
+  }
+};
+
+template <int... I>
+Table2<I...> make_table2(std::integer_sequence<int, I...>);
+
 using KernelFn = void (*)(OrthoArgs, ReduceWork);
 using FinishFn = void (*)(OrthoArgs, ReduceWork, int);
 
@@ -207,6 +386,32 @@ void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st, hipE
   else
     hipLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, a, rw);
   hipLaunchKernelGGL(T::fin(a.nv), dim3(1), dim3(NF), 0, st, a, rw, nb);
+}
+
+int dcgs2_blocks(long len, const ReduceWork& rw) {
+  long blocks = (len + NT - 1) / NT;
+  if (blocks > rw.max_blocks) blocks = rw.max_blocks;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+void launch_dcgs2_dots(const D2Args& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  using T = decltype(make_table2(std::make_integer_sequence<int, kMaxDcgs2 + 1>{}));
+  const int nb = dcgs2_blocks(a.len, rw);
+  if (ev0)
+    hipExtLaunchKernelGGL(T::dots(a.nv), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a, rw);
+  else
+    hipLaunchKernelGGL(T::dots(a.nv), dim3(nb), dim3(NT), 0, st, a, rw);
+  hipLaunchKernelGGL(T::fin(a.nv), dim3(1), dim3(NF2), 0, st, a, rw, nb);
+}
+
+void launch_dcgs2_update(const D2Args& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  using T = decltype(make_table2(std::make_integer_sequence<int, kMaxDcgs2 + 1>{}));
+  const int nb = dcgs2_blocks(a.len, rw);
+  if (ev0)
+    hipExtLaunchKernelGGL(T::upd(a.nv), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a);
+  else
+    hipLaunchKernelGGL(T::upd(a.nv), dim3(nb), dim3(NT), 0, st, a);
 }
 
 }  // namespace irk

@@ -47,28 +47,6 @@ __device__ __forceinline__ TC diag_at(const TC* K, int li, int lj, TC m, TC alph
 }
 
 
-// Tile loads are staged through registers with fully unrolled loops, so every
-// thread has all of its global loads in flight before the first LDS store.
-template <typename TC, typename TK, int KX, int KY>
-__device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ kap, int ox, int oy, const Geom& g) {
-  constexpr int CNT = KX * KY, NL = (CNT + NT - 1) / NT;
-  TC v[NL];
-#pragma unroll
-  for (int r = 0; r < NL; ++r) {
-    const int idx = threadIdx.x + r * NT;
-    const int b = idx / KX, a = idx - b * KX;
-    const int ex = ox - 1 + a, ey = oy - 1 + b;
-    const bool ok = idx < CNT && ex >= 0 && ex < g.N && ey >= 0 && ey < g.N;
-    // unconditional load from a clamped address keeps all loads in flight; the select zeroes the rest
-    const TC val = (TC)kap[ok ? (long)ey * g.pitch + ex : 0];
-    v[r] = ok ? val : (TC)0;
-  }
-#pragma unroll
-  for (int r = 0; r < NL; ++r) {
-    const int idx = threadIdx.x + r * NT;
-    if (idx < CNT) sK[idx] = v[r];
-  }
-}
 
 
 // Block-triangular stage coupling inside the finest-level tiles: w = sum_q a_q z_q is loaded on the
@@ -368,19 +346,30 @@ __global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t,
   }
 }
 
-constexpr int TXD = 64, TYD = 16;
+// Tiles: 64 x 16 on large levels (coalesced rows, small halo share); on levels below 512^2, where a
+// level is latency-bound, 32 x 8 tiles spread the work of each smoothing phase over four times more
+// waves.
+constexpr int TXD = 64, TYD = 16, TXS = 32, TYS = 8;
+constexpr int kSmallLevel = 512;
+
+template <typename TV, typename TS, typename TC, bool CP, int TX, int TY>
+void down_tiles(const TV* tt, const double* tscale, TS* xx, TS* cc, const TC* kk, Geom g, Geom gc, const MGCoef& c,
+                const Couple& cp, hipStream_t st) {
+  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  switch (c.deg) {
+    case 1: mg_down_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
+    case 2: mg_down_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
+    default: mg_down_kernel<TV, TS, TC, 3, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
+  }
+}
 
 template <typename TV, typename TS, typename TC, bool CP>
 void down_launch(const TV* tt, const double* tscale, TS* xx, TS* cc, const TC* kk, Geom g, Geom gc, const MGCoef& c,
                  const Couple& cp, hipStream_t st) {
-  const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
-  switch (c.deg) {
-    case 1: mg_down_kernel<TV, TS, TC, 1, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
-    case 2: mg_down_kernel<TV, TS, TC, 2, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
-    default:
-      mg_down_kernel<TV, TS, TC, 3, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp);
-      break;
-  }
+  if (g.N < kSmallLevel)
+    down_tiles<TV, TS, TC, CP, TXS, TYS>(tt, tscale, xx, cc, kk, g, gc, c, cp, st);
+  else
+    down_tiles<TV, TS, TC, CP, TXD, TYD>(tt, tscale, xx, cc, kk, g, gc, c, cp, st);
 }
 
 template <typename TV, typename TS, typename TC>
@@ -392,17 +381,24 @@ void down_t(const void* t, const double* tscale, void* x, void* tc, const void* 
     down_launch<TV, TS, TC, false>((const TV*)t, tscale, (TS*)x, (TS*)tc, (const TC*)kap, g, gc, c, cp, st);
 }
 
+template <typename TV, typename TS, typename TC, bool CP, int TX, int TY>
+void up_tiles(const TV* tt, const double* tscale, const TS* xx, const TS* ee, TV* oo, const TC* kk, Geom g, Geom gc,
+              const MGCoef& c, const Couple& cp, hipStream_t st) {
+  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  switch (c.deg) {
+    case 1: mg_up_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
+    case 2: mg_up_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
+    default: mg_up_kernel<TV, TS, TC, 3, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
+  }
+}
+
 template <typename TV, typename TS, typename TC, bool CP>
 void up_launch(const TV* tt, const double* tscale, const TS* xx, const TS* ee, TV* oo, const TC* kk, Geom g, Geom gc,
                const MGCoef& c, const Couple& cp, hipStream_t st) {
-  const dim3 grid((g.N - 1 + TXD - 1) / TXD, (g.N - 1 + TYD - 1) / TYD);
-  switch (c.deg) {
-    case 1: mg_up_kernel<TV, TS, TC, 1, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
-    case 2: mg_up_kernel<TV, TS, TC, 2, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
-    default:
-      mg_up_kernel<TV, TS, TC, 3, TXD, TYD, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp);
-      break;
-  }
+  if (g.N < kSmallLevel)
+    up_tiles<TV, TS, TC, CP, TXS, TYS>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp, st);
+  else
+    up_tiles<TV, TS, TC, CP, TXD, TYD>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp, st);
 }
 
 template <typename TV, typename TS, typename TC>

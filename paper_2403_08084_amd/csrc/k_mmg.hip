@@ -10,9 +10,9 @@
 // iteration. One thread owns one node and all of its stages, so the s x s stage mixing
 // never leaves registers.
 //
-// Kernels per level of a V-cycle: one Chebyshev step per smoothing step (stencil, block
-// solve, recurrence), the residual, the full-weighting restriction, the bilinear
-// prolongation-and-correction, and on the coarsest level a dense inverse.
+// Kernels per level of a V-cycle: a fused DOWN (pre-smoothing, residual, restriction) and a
+// fused UP (prolongation and correction, post-smoothing), both LDS-tiled; on the coarsest level
+// a dense inverse.
 #include "mg_device.h"
 
 namespace irk {
@@ -126,86 +126,337 @@ __device__ __forceinline__ void block_solve(TC C[S][S], TC r[S]) {
   }
 }
 
-// One Chebyshev step of the additive-Schwarz-preconditioned iteration on a level:
-//   step 0:  out = xc + c0 C^{-1} (ts t - Acal xc)               (xc == nullptr: xc = 0)
-//   step k:  out = xc + beta_k (xc - xp) + gam_k C^{-1} (ts t - Acal xc)   (xp == nullptr: xp = 0)
-// out may alias xp (read and written only at the thread's own node).
-template <typename TT, typename TS, typename TO, typename TC, int S>
-__global__ __launch_bounds__(MX* MY) void mmg_step_kernel(const TT* __restrict__ t, const double* __restrict__ tscale,
-                                                          const TS* __restrict__ xc, const TS* xp, TO* out,
-                                                          const TC* __restrict__ kap, Geom g, MMGCoef c, int step) {
-  int i, j;
-  if (!mmg_node(g, i, j)) return;
-  const long p = (long)j * g.pitch + i;
-  const Stencil<TC> k = load_stencil(kap, p, g.pitch);
-  const TC ts = tscale ? (TC)(*tscale) : (TC)1;
-  TC r[S];
-  residual_at<TT, TS, TC, S>(t, ts, xc, p, g, k, c, r);
-  TC C[S][S];
-  patch_block<TC, S>(c, k.kdiag(), C);
-  block_solve<TC, S>(C, r);
-  if (step == 0) {
-    const TC c0 = (TC)c.c0;
+// z = C_v^{-1} r in place from the closed form w adj(I + tau B) / det(I + tau B) (coefficients precomputed
+// per level on the host); kd = K_vv of the node
+template <typename TC, int S>
+__device__ __forceinline__ void patch_apply(const MMGCoef& c, TC kd, TC r[S]) {
+  const TC tau = c.ia ? (TC)c.tfac / kd : (TC)c.tfac * kd;
+  const TC w = c.ia ? (TC)c.wfac / kd : (TC)c.wfac;
+  TC d = (TC)c.det[S];
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-      const TC x0 = xc ? ld<TC>(xc + q * g.plane + p) : (TC)0;
-      st(out + q * g.plane + p, x0 + c0 * r[q]);
+  for (int k = S - 1; k >= 0; --k) d = d * tau + (TC)c.det[k];
+  const TC f = w / d;
+  TC z[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    TC acc = (TC)0;
+#pragma unroll
+    for (int rr = 0; rr < S; ++rr) {
+      TC a = (TC)c.adj[(S - 1) * kMMGMax * kMMGMax + q * kMMGMax + rr];
+#pragma unroll
+      for (int k = S - 2; k >= 0; --k) a = a * tau + (TC)c.adj[k * kMMGMax * kMMGMax + q * kMMGMax + rr];
+      acc += a * r[rr];
+    }
+    z[q] = f * acc;
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q) r[q] = z[q];
+}
+
+// ---------------------------------------------------------------- fused, LDS-tiled levels
+//
+// One level of the V-cycle is two kernels, as for the single-stage cycle:
+//   DOWN: Chebyshev pre-smoothing from zero, the residual and its restriction (I (x) P^T);
+//         writes the smoothed iterate and the coarse right-hand side.
+//   UP:   prolongation and correction x + (I (x) P) e, then Chebyshev post-smoothing.
+// A block stages a TX x TY tile plus a halo of all s planes (right-hand side and two iterates)
+// and the element diffusivities in LDS; the valid region shrinks by one node per stencil.
+
+// (Acal x)_q at LDS node (li, lj) of S planes (plane stride PA, row length RX); kd = K_vv
+template <typename TC, int S, int RX, int KX, int PA>
+__device__ __forceinline__ void lds_apply(const TC* X, const TC* sK, int li, int lj, const MMGCoef& c, TC out[S],
+                                          TC& kd) {
+  const int p = lj * RX + li;
+  const int q = lj * KX + li;
+  const TC kSW = sK[q], kSE = sK[q + 1], kNW = sK[q + KX], kNE = sK[q + KX + 1];
+  const TC ks = kSW + kSE + kNW + kNE;
+  kd = (TC)(2.0 / 3.0) * ks;
+  const TC m = (TC)c.m, dt = (TC)c.dt;
+  TC Mx[S], Kx[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const TC* x = X + r * PA + p;
+    const TC xc = x[0], xE = x[1], xW = x[-1], xN = x[RX], xS = x[-RX];
+    const TC xNE = x[RX + 1], xNW = x[RX - 1], xSE = x[-RX + 1], xSW = x[-RX - 1];
+    Kx[r] = kd * xc -
+            (TC)(1.0 / 6.0) * ((kNE + kSE) * xE + (kNW + kSW) * xW + (kNE + kNW) * xN + (kSE + kSW) * xS) -
+            (TC)(1.0 / 3.0) * (kNE * xNE + kNW * xNW + kSE * xSE + kSW * xSW);
+    Mx[r] = m * ((TC)16 * xc + (TC)4 * (xE + xW + xN + xS) + (xNE + xNW + xSE + xSW));
+  }
+  // one of the two mixing matrices is the identity: AI (I, ck), IA (cm, I)
+  if (c.ia) {
+#pragma unroll
+    for (int qq = 0; qq < S; ++qq) {
+      TC acc = dt * Kx[qq];
+#pragma unroll
+      for (int r = 0; r < S; ++r) acc += (TC)c.cm[qq * kMMGMax + r] * Mx[r];
+      out[qq] = acc;
     }
   } else {
-    const TC beta = (TC)c.beta[step], gam = (TC)c.gam[step];
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-      const TC x1 = ld<TC>(xc + q * g.plane + p);
-      const TC x0 = xp ? ld<TC>(xp + q * g.plane + p) : (TC)0;
-      st(out + q * g.plane + p, x1 + beta * (x1 - x0) + gam * r[q]);
+    for (int qq = 0; qq < S; ++qq) {
+      TC acc = (TC)0;
+#pragma unroll
+      for (int r = 0; r < S; ++r) acc += (TC)c.ck[qq * kMMGMax + r] * Kx[r];
+      out[qq] = Mx[qq] + dt * acc;
     }
   }
 }
 
-// r = ts t - Acal x into level storage
-template <typename TT, typename TS, typename TC, int S>
-__global__ __launch_bounds__(MX* MY) void mmg_residual_kernel(const TT* __restrict__ t, const double* __restrict__ tscale,
-                                                              const TS* __restrict__ x, TS* __restrict__ rout,
-                                                              const TC* __restrict__ kap, Geom g, MMGCoef c) {
-  int i, j;
-  if (!mmg_node(g, i, j)) return;
-  const long p = (long)j * g.pitch + i;
-  const Stencil<TC> k = load_stencil(kap, p, g.pitch);
-  const TC ts = tscale ? (TC)(*tscale) : (TC)1;
-  TC r[S];
-  residual_at<TT, TS, TC, S>(t, ts, x, p, g, k, c, r);
-#pragma unroll
-  for (int q = 0; q < S; ++q) st(rout + q * g.plane + p, r[q]);
+template <typename TC, int KX>
+__device__ __forceinline__ TC lds_kdiag(const TC* sK, int li, int lj) {
+  const int q = lj * KX + li;
+  return (TC)(2.0 / 3.0) * (sK[q] + sK[q + 1] + sK[q + KX] + sK[q + KX + 1]);
 }
 
-// coarse right-hand side = (I (x) P^T) r, full weighting around fine node (2I, 2J)
-template <typename TS, typename TC, int S>
-__global__ __launch_bounds__(MX* MY) void mmg_restrict_kernel(const TS* __restrict__ r, TS* __restrict__ tc, Geom g,
-                                                              Geom gc) {
-  int I, J;
-  if (!mmg_node(gc, I, J)) return;
-  const int P = g.pitch;
-  const long f = (long)(2 * J) * P + 2 * I;
+// Tiles: on large levels 64 wide (coalesced rows) and tall enough to amortise the halo while keeping the
+// three S-plane LDS fields within about 80 KB; on levels below 512^2 a 32 x 8 tile spreads the
+// latency-bound work over four times more waves.
+template <typename TC, int S, bool SMALL>
+struct MTile {
+  static constexpr int TX = SMALL ? 32 : 64;
+  static constexpr int TY = 8;
+};
+constexpr int kSmallLevel = 512;
+
+template <typename TT, typename TS, typename TC, int S, int DEG, int TX, int TY>
+__global__ __launch_bounds__(NT) void mmg_down_kernel(const TT* __restrict__ t, const double* __restrict__ tscale,
+                                                      TS* __restrict__ xout, TS* __restrict__ tc,
+                                                      const TC* __restrict__ kap, Geom g, Geom gc, MMGCoef c) {
+  constexpr int H = DEG + 1;
+  constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
+  constexpr int KX = RX + 1, KY = RY + 1;
+  constexpr int PA = RX * RY;
+  __shared__ TC sK[KX * KY];
+  __shared__ TC sT[S * PA];
+  __shared__ TC sA[S * PA];
+  __shared__ TC sB[S * PA];
+  const int N = g.N;
+  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  const int ox = i0 - H, oy = j0 - H;
+  const TC ts = tscale ? (TC)(*tscale) : (TC)1;
+  {
+    constexpr int NL = (PA + NT - 1) / NT;
+    TC tv[S][NL];
 #pragma unroll
-  for (int q = 0; q < S; ++q) {
-    const TS* R = r + q * g.plane + f;
-    const TC v = ld<TC>(R) + (TC)0.5 * (ld<TC>(R + 1) + ld<TC>(R - 1) + ld<TC>(R + P) + ld<TC>(R - P)) +
-                 (TC)0.25 * (ld<TC>(R + P + 1) + ld<TC>(R + P - 1) + ld<TC>(R - P + 1) + ld<TC>(R - P - 1));
-    st(tc + q * gc.plane + (long)J * gc.pitch + I, v);
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        const int lj = idx / RX, li = idx - lj * RX;
+        const int i = ox + li, j = oy + lj;
+        const bool ok = idx < PA && interior(i, j, N);
+        const TC val = ld<TC>(t + q * g.plane + (ok ? (long)j * g.pitch + i : 0));
+        tv[q][r] = ok ? val * ts : (TC)0;
+      }
+    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        if (idx < PA) sT[q * PA + idx] = tv[q][r];
+      }
+  }
+  __syncthreads();
+  // step 0 from x = 0 is pointwise: x1 = c0 C^{-1} t on the whole region
+  {
+    const TC c0 = (TC)c.c0;
+    for (int idx = threadIdx.x; idx < PA; idx += NT) {
+      const int lj = idx / RX, li = idx - lj * RX;
+      TC r[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) r[q] = sT[q * PA + idx];
+      const bool in = interior(ox + li, oy + lj, N);
+      if (in) patch_apply<TC, S>(c, lds_kdiag<TC, KX>(sK, li, lj), r);
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        sB[q * PA + idx] = in ? c0 * r[q] : (TC)0;
+        sA[q * PA + idx] = (TC)0;
+      }
+    }
+  }
+  __syncthreads();
+  TC* cur = sB;
+  TC* prv = sA;
+#pragma unroll
+  for (int k = 1; k < DEG; ++k) {
+    const TC beta = (TC)c.beta[k], gam = (TC)c.gam[k];
+    const int w = RX - 2 * k, hgt = RY - 2 * k;
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = k + idx / w, li = k + idx % w;
+      if (!interior(ox + li, oy + lj, N)) continue;
+      const int p = lj * RX + li;
+      TC ax[S], kd;
+      lds_apply<TC, S, RX, KX, PA>(cur, sK, li, lj, c, ax, kd);
+      TC r[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) r[q] = sT[q * PA + p] - ax[q];
+      patch_apply<TC, S>(c, kd, r);
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const TC x1 = cur[q * PA + p];
+        prv[q * PA + p] = x1 + beta * (x1 - prv[q * PA + p]) + gam * r[q];
+      }
+    }
+    __syncthreads();
+    TC* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  // smoothed iterate on the tile
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int lj = H + idx / TX, li = H + idx % TX;
+    const int i = ox + li, j = oy + lj;
+    if (interior(i, j, N)) {
+#pragma unroll
+      for (int q = 0; q < S; ++q) st(xout + q * g.plane + (long)j * g.pitch + i, cur[q * PA + lj * RX + li]);
+    }
+  }
+  // residual on the tile plus one node
+  {
+    const int w = TX + 2, hgt = TY + 2;
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = H - 1 + idx / w, li = H - 1 + idx % w;
+      const int p = lj * RX + li;
+      TC r[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) r[q] = (TC)0;
+      if (interior(ox + li, oy + lj, N)) {
+        TC ax[S], kd;
+        lds_apply<TC, S, RX, KX, PA>(cur, sK, li, lj, c, ax, kd);
+#pragma unroll
+        for (int q = 0; q < S; ++q) r[q] = sT[q * PA + p] - ax[q];
+      }
+#pragma unroll
+      for (int q = 0; q < S; ++q) prv[q * PA + p] = r[q];
+    }
+  }
+  __syncthreads();
+  // full-weighting restriction of every plane to the coarse nodes centred in the tile
+  {
+    constexpr int CX = TX / 2, CY = TY / 2;
+    const int I0 = (i0 + 1) / 2, J0 = (j0 + 1) / 2;
+    for (int idx = threadIdx.x; idx < CX * CY; idx += NT) {
+      const int I = I0 + idx % CX, J = J0 + idx / CX;
+      if (I > gc.N - 1 || J > gc.N - 1) continue;
+      const int li = 2 * I - ox, lj = 2 * J - oy;
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const TC* R = prv + q * PA + lj * RX + li;
+        const TC v = R[0] + (TC)0.5 * (R[1] + R[-1] + R[RX] + R[-RX]) +
+                     (TC)0.25 * (R[RX + 1] + R[RX - 1] + R[-RX + 1] + R[-RX - 1]);
+        st(tc + q * gc.plane + (long)J * gc.pitch + I, v);
+      }
+    }
   }
 }
 
-// x += (I (x) P) e
-template <typename TS, typename TC, int S>
-__global__ __launch_bounds__(MX* MY) void mmg_prolong_kernel(const TS* __restrict__ e, TS* __restrict__ x, Geom g,
-                                                             Geom gc) {
-  int i, j;
-  if (!mmg_node(g, i, j)) return;
-  const long p = (long)j * g.pitch + i;
+template <typename TT, typename TS, typename TO, typename TC, int S, int DEG, int TX, int TY>
+__global__ __launch_bounds__(NT) void mmg_up_kernel(const TT* __restrict__ t, const double* __restrict__ tscale,
+                                                    const TS* __restrict__ x, const TS* __restrict__ e,
+                                                    TO* __restrict__ out, const TC* __restrict__ kap, Geom g, Geom gc,
+                                                    MMGCoef c) {
+  constexpr int H = DEG;
+  constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
+  constexpr int KX = RX + 1, KY = RY + 1;
+  constexpr int PA = RX * RY;
+  __shared__ TC sK[KX * KY];
+  __shared__ TC sT[S * PA];
+  __shared__ TC sA[S * PA];
+  __shared__ TC sB[S * PA];
+  const int N = g.N;
+  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  const int ox = i0 - H, oy = j0 - H;
+  const TC ts = tscale ? (TC)(*tscale) : (TC)1;
+  {
+    constexpr int NL = (PA + NT - 1) / NT;
+    TC tv[S][NL], xv[S][NL];
 #pragma unroll
-  for (int q = 0; q < S; ++q) {
-    TS* xp = x + q * g.plane + p;
-    st(xp, ld<TC>(xp) + prolong_at<TS, TC>(e + q * gc.plane, gc.pitch, i, j));
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        const int lj = idx / RX, li = idx - lj * RX;
+        const int i = ox + li, j = oy + lj;
+        const bool ok = idx < PA && interior(i, j, N);
+        const int ic = ok ? i : 1, jc = ok ? j : 1;
+        const long p = (long)jc * g.pitch + ic;
+        const TC a = ld<TC>(t + q * g.plane + p) * ts;
+        const TC b = ld<TC>(x + q * g.plane + p) + prolong_at<TS, TC>(e + q * gc.plane, gc.pitch, ic, jc);
+        tv[q][r] = ok ? a : (TC)0;
+        xv[q][r] = ok ? b : (TC)0;
+      }
+    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int r = 0; r < NL; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        if (idx < PA) {
+          sT[q * PA + idx] = tv[q][r];
+          sA[q * PA + idx] = xv[q][r];
+        }
+      }
+  }
+  __syncthreads();
+  // step 0 from the corrected iterate: x1 = x0 + c0 C^{-1} (t - Acal x0) on the inner region
+  {
+    const TC c0 = (TC)c.c0;
+    const int w = RX - 2, hgt = RY - 2;
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = 1 + idx / w, li = 1 + idx % w;
+      const int p = lj * RX + li;
+      if (interior(ox + li, oy + lj, N)) {
+        TC ax[S], kd;
+        lds_apply<TC, S, RX, KX, PA>(sA, sK, li, lj, c, ax, kd);
+        TC r[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) r[q] = sT[q * PA + p] - ax[q];
+        patch_apply<TC, S>(c, kd, r);
+#pragma unroll
+        for (int q = 0; q < S; ++q) sB[q * PA + p] = sA[q * PA + p] + c0 * r[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < S; ++q) sB[q * PA + p] = (TC)0;
+      }
+    }
+  }
+  __syncthreads();
+  TC* cur = sB;
+  TC* prv = sA;
+#pragma unroll
+  for (int k = 1; k < DEG; ++k) {
+    const TC beta = (TC)c.beta[k], gam = (TC)c.gam[k];
+    const int w = RX - 2 * (k + 1), hgt = RY - 2 * (k + 1);
+    for (int idx = threadIdx.x; idx < w * hgt; idx += NT) {
+      const int lj = k + 1 + idx / w, li = k + 1 + idx % w;
+      if (!interior(ox + li, oy + lj, N)) continue;
+      const int p = lj * RX + li;
+      TC ax[S], kd;
+      lds_apply<TC, S, RX, KX, PA>(cur, sK, li, lj, c, ax, kd);
+      TC r[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) r[q] = sT[q * PA + p] - ax[q];
+      patch_apply<TC, S>(c, kd, r);
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const TC x1 = cur[q * PA + p];
+        prv[q * PA + p] = x1 + beta * (x1 - prv[q * PA + p]) + gam * r[q];
+      }
+    }
+    __syncthreads();
+    TC* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int lj = H + idx / TX, li = H + idx % TX;
+    const int i = ox + li, j = oy + lj;
+    if (interior(i, j, N)) {
+#pragma unroll
+      for (int q = 0; q < S; ++q) st(out + q * g.plane + (long)j * g.pitch + i, cur[q * PA + lj * RX + li]);
+    }
   }
 }
 
@@ -278,107 +529,110 @@ __global__ __launch_bounds__(MX* MY) void mmg_apply_kernel(const double* __restr
 
 // ---------------------------------------------------------------- launch dispatch
 
-template <typename TT, typename TS, typename TO, typename TC>
-void step_t(const void* t, const double* ts, const void* xc, const void* xp, void* out, const void* kap, Geom g,
-            const MMGCoef& c, int step, hipStream_t st) {
-  const dim3 grid = mmg_grid(g), blk(MX, MY);
-  const TT* tt = (const TT*)t;
-  const TS *a = (const TS*)xc, *b = (const TS*)xp;
-  TO* o = (TO*)out;
-  const TC* k = (const TC*)kap;
-  switch (c.s) {
-    case 1: mmg_step_kernel<TT, TS, TO, TC, 1><<<grid, blk, 0, st>>>(tt, ts, a, b, o, k, g, c, step); break;
-    case 2: mmg_step_kernel<TT, TS, TO, TC, 2><<<grid, blk, 0, st>>>(tt, ts, a, b, o, k, g, c, step); break;
-    case 3: mmg_step_kernel<TT, TS, TO, TC, 3><<<grid, blk, 0, st>>>(tt, ts, a, b, o, k, g, c, step); break;
-    default: mmg_step_kernel<TT, TS, TO, TC, 4><<<grid, blk, 0, st>>>(tt, ts, a, b, o, k, g, c, step); break;
+template <typename TT, typename TS, typename TC, int S, int DEG, bool SMALL>
+void down_k(const void* t, const double* ts, void* x, void* tc, const void* kap, Geom g, Geom gc, const MMGCoef& c,
+            hipStream_t st) {
+  constexpr int TX = MTile<TC, S, SMALL>::TX, TY = MTile<TC, S, SMALL>::TY;
+  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  mmg_down_kernel<TT, TS, TC, S, DEG, TX, TY><<<grid, NT, 0, st>>>((const TT*)t, ts, (TS*)x, (TS*)tc, (const TC*)kap,
+                                                                   g, gc, c);
+}
+
+template <typename TT, typename TS, typename TO, typename TC, int S, int DEG, bool SMALL>
+void up_k(const void* t, const double* ts, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
+          const MMGCoef& c, hipStream_t st) {
+  constexpr int TX = MTile<TC, S, SMALL>::TX, TY = MTile<TC, S, SMALL>::TY;
+  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  mmg_up_kernel<TT, TS, TO, TC, S, DEG, TX, TY><<<grid, NT, 0, st>>>((const TT*)t, ts, (const TS*)x, (const TS*)e,
+                                                                     (TO*)out, (const TC*)kap, g, gc, c);
+}
+
+template <typename TT, typename TS, typename TC, int S, int DEG>
+void down_s(const void* t, const double* ts, void* x, void* tc, const void* kap, Geom g, Geom gc, const MMGCoef& c,
+            hipStream_t st) {
+  if (g.N < kSmallLevel)
+    down_k<TT, TS, TC, S, DEG, true>(t, ts, x, tc, kap, g, gc, c, st);
+  else
+    down_k<TT, TS, TC, S, DEG, false>(t, ts, x, tc, kap, g, gc, c, st);
+}
+
+template <typename TT, typename TS, typename TO, typename TC, int S, int DEG>
+void up_s(const void* t, const double* ts, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
+          const MMGCoef& c, hipStream_t st) {
+  if (g.N < kSmallLevel)
+    up_k<TT, TS, TO, TC, S, DEG, true>(t, ts, x, e, out, kap, g, gc, c, st);
+  else
+    up_k<TT, TS, TO, TC, S, DEG, false>(t, ts, x, e, out, kap, g, gc, c, st);
+}
+
+template <typename TT, typename TS, typename TC, int S>
+void down_d(const void* t, const double* ts, void* x, void* tc, const void* kap, Geom g, Geom gc, const MMGCoef& c,
+            hipStream_t st) {
+  switch (c.deg) {
+    case 1: down_s<TT, TS, TC, S, 1>(t, ts, x, tc, kap, g, gc, c, st); break;
+    case 2: down_s<TT, TS, TC, S, 2>(t, ts, x, tc, kap, g, gc, c, st); break;
+    default: down_s<TT, TS, TC, S, 3>(t, ts, x, tc, kap, g, gc, c, st); break;
+  }
+}
+
+template <typename TT, typename TS, typename TO, typename TC, int S>
+void up_d(const void* t, const double* ts, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
+          const MMGCoef& c, hipStream_t st) {
+  switch (c.deg) {
+    case 1: up_s<TT, TS, TO, TC, S, 1>(t, ts, x, e, out, kap, g, gc, c, st); break;
+    case 2: up_s<TT, TS, TO, TC, S, 2>(t, ts, x, e, out, kap, g, gc, c, st); break;
+    default: up_s<TT, TS, TO, TC, S, 3>(t, ts, x, e, out, kap, g, gc, c, st); break;
   }
 }
 
 template <typename TT, typename TS, typename TC>
-void residual_t(const void* t, const double* ts, const void* x, void* r, const void* kap, Geom g, const MMGCoef& c,
-                hipStream_t st) {
-  const dim3 grid = mmg_grid(g), blk(MX, MY);
-  const TT* tt = (const TT*)t;
-  const TS* xx = (const TS*)x;
-  TS* rr = (TS*)r;
-  const TC* k = (const TC*)kap;
+void down_t(const void* t, const double* ts, void* x, void* tc, const void* kap, Geom g, Geom gc, const MMGCoef& c,
+            hipStream_t st) {
   switch (c.s) {
-    case 1: mmg_residual_kernel<TT, TS, TC, 1><<<grid, blk, 0, st>>>(tt, ts, xx, rr, k, g, c); break;
-    case 2: mmg_residual_kernel<TT, TS, TC, 2><<<grid, blk, 0, st>>>(tt, ts, xx, rr, k, g, c); break;
-    case 3: mmg_residual_kernel<TT, TS, TC, 3><<<grid, blk, 0, st>>>(tt, ts, xx, rr, k, g, c); break;
-    default: mmg_residual_kernel<TT, TS, TC, 4><<<grid, blk, 0, st>>>(tt, ts, xx, rr, k, g, c); break;
+    case 1: down_d<TT, TS, TC, 1>(t, ts, x, tc, kap, g, gc, c, st); break;
+    case 2: down_d<TT, TS, TC, 2>(t, ts, x, tc, kap, g, gc, c, st); break;
+    case 3: down_d<TT, TS, TC, 3>(t, ts, x, tc, kap, g, gc, c, st); break;
+    default: down_d<TT, TS, TC, 4>(t, ts, x, tc, kap, g, gc, c, st); break;
   }
 }
 
-template <typename TS, typename TC>
-void transfer_t(bool restrict_, const void* a, void* b, Geom g, Geom gc, int s, hipStream_t st) {
-  const dim3 blk(MX, MY);
-  if (restrict_) {
-    const dim3 grid = mmg_grid(gc);
-    const TS* r = (const TS*)a;
-    TS* tc = (TS*)b;
-    switch (s) {
-      case 1: mmg_restrict_kernel<TS, TC, 1><<<grid, blk, 0, st>>>(r, tc, g, gc); break;
-      case 2: mmg_restrict_kernel<TS, TC, 2><<<grid, blk, 0, st>>>(r, tc, g, gc); break;
-      case 3: mmg_restrict_kernel<TS, TC, 3><<<grid, blk, 0, st>>>(r, tc, g, gc); break;
-      default: mmg_restrict_kernel<TS, TC, 4><<<grid, blk, 0, st>>>(r, tc, g, gc); break;
-    }
-  } else {
-    const dim3 grid = mmg_grid(g);
-    const TS* e = (const TS*)a;
-    TS* x = (TS*)b;
-    switch (s) {
-      case 1: mmg_prolong_kernel<TS, TC, 1><<<grid, blk, 0, st>>>(e, x, g, gc); break;
-      case 2: mmg_prolong_kernel<TS, TC, 2><<<grid, blk, 0, st>>>(e, x, g, gc); break;
-      case 3: mmg_prolong_kernel<TS, TC, 3><<<grid, blk, 0, st>>>(e, x, g, gc); break;
-      default: mmg_prolong_kernel<TS, TC, 4><<<grid, blk, 0, st>>>(e, x, g, gc); break;
-    }
+template <typename TT, typename TS, typename TO, typename TC>
+void up_t(const void* t, const double* ts, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
+          const MMGCoef& c, hipStream_t st) {
+  switch (c.s) {
+    case 1: up_d<TT, TS, TO, TC, 1>(t, ts, x, e, out, kap, g, gc, c, st); break;
+    case 2: up_d<TT, TS, TO, TC, 2>(t, ts, x, e, out, kap, g, gc, c, st); break;
+    case 3: up_d<TT, TS, TO, TC, 3>(t, ts, x, e, out, kap, g, gc, c, st); break;
+    default: up_d<TT, TS, TO, TC, 4>(t, ts, x, e, out, kap, g, gc, c, st); break;
   }
 }
 
 }  // namespace
 
 // prec: 0 FP64, 1 FP32, 2 BF16 storage with FP32 compute (kappa and Cinv in the compute type).
-// t_f64 / out_f64: t or out is an FP64 Krylov vector instead of level storage.
-void launch_mmg_step(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, const void* xc,
-                     const void* xp, void* out, const void* kap, Geom g, const MMGCoef& c, int step, hipStream_t st) {
-  if (prec == 0) {
-    step_t<double, double, double, double>(t, tscale, xc, xp, out, kap, g, c, step, st);
-  } else if (prec == 1) {
-    if (t_f64 && out_f64) step_t<double, float, double, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-    else if (t_f64) step_t<double, float, float, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-    else if (out_f64) step_t<float, float, double, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-    else step_t<float, float, float, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-  } else {
-    if (t_f64 && out_f64) step_t<double, bf16, double, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-    else if (t_f64) step_t<double, bf16, bf16, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-    else if (out_f64) step_t<bf16, bf16, double, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-    else step_t<bf16, bf16, bf16, float>(t, tscale, xc, xp, out, kap, g, c, step, st);
-  }
-}
-
-void launch_mmg_residual(int prec, bool t_f64, const void* t, const double* tscale, const void* x, void* r,
-                         const void* kap, Geom g, const MMGCoef& c, hipStream_t st) {
-  if (prec == 0) residual_t<double, double, double>(t, tscale, x, r, kap, g, c, st);
+// t_f64: t (and, for UP, out) is an FP64 Krylov vector (the finest level) instead of level storage.
+void launch_mmg_down(int prec, bool t_f64, const void* t, const double* tscale, void* x, void* tc, const void* kap,
+                     Geom g, Geom gc, const MMGCoef& c, hipStream_t st) {
+  if (prec == 0) down_t<double, double, double>(t, tscale, x, tc, kap, g, gc, c, st);
   else if (prec == 1) {
-    if (t_f64) residual_t<double, float, float>(t, tscale, x, r, kap, g, c, st);
-    else residual_t<float, float, float>(t, tscale, x, r, kap, g, c, st);
+    if (t_f64) down_t<double, float, float>(t, tscale, x, tc, kap, g, gc, c, st);
+    else down_t<float, float, float>(t, tscale, x, tc, kap, g, gc, c, st);
   } else {
-    if (t_f64) residual_t<double, bf16, float>(t, tscale, x, r, kap, g, c, st);
-    else residual_t<bf16, bf16, float>(t, tscale, x, r, kap, g, c, st);
+    if (t_f64) down_t<double, bf16, float>(t, tscale, x, tc, kap, g, gc, c, st);
+    else down_t<bf16, bf16, float>(t, tscale, x, tc, kap, g, gc, c, st);
   }
 }
 
-void launch_mmg_restrict(int prec, const void* r, void* tc, Geom g, Geom gc, int s, hipStream_t st) {
-  if (prec == 0) transfer_t<double, double>(true, r, tc, g, gc, s, st);
-  else if (prec == 1) transfer_t<float, float>(true, r, tc, g, gc, s, st);
-  else transfer_t<bf16, float>(true, r, tc, g, gc, s, st);
-}
-
-void launch_mmg_prolong(int prec, const void* e, void* x, Geom g, Geom gc, int s, hipStream_t st) {
-  if (prec == 0) transfer_t<double, double>(false, e, x, g, gc, s, st);
-  else if (prec == 1) transfer_t<float, float>(false, e, x, g, gc, s, st);
-  else transfer_t<bf16, float>(false, e, x, g, gc, s, st);
+void launch_mmg_up(int prec, bool io_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
+                   const void* kap, Geom g, Geom gc, const MMGCoef& c, hipStream_t st) {
+  if (prec == 0) up_t<double, double, double, double>(t, tscale, x, e, out, kap, g, gc, c, st);
+  else if (prec == 1) {
+    if (io_f64) up_t<double, float, double, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+    else up_t<float, float, float, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+  } else {
+    if (io_f64) up_t<double, bf16, double, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+    else up_t<bf16, bf16, bf16, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+  }
 }
 
 void launch_mmg_coarse(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, void* out,

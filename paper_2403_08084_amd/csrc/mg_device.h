@@ -44,5 +44,28 @@ __device__ __forceinline__ TC prolong_at(const TS* __restrict__ e, int pc, int i
   return ((TC)1 - wx) * ((TC)1 - wy) * e00 + wx * ((TC)1 - wy) * e10 + ((TC)1 - wx) * wy * e01 + wx * wy * e11;
 }
 
+// Tile loads are staged through registers with fully unrolled loops, so every
+// thread has all of its global loads in flight before the first LDS store.
+template <typename TC, typename TK, int KX, int KY>
+__device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ kap, int ox, int oy, const Geom& g) {
+  constexpr int CNT = KX * KY, NL = (CNT + NT - 1) / NT;
+  TC v[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    const int b = idx / KX, a = idx - b * KX;
+    const int ex = ox - 1 + a, ey = oy - 1 + b;
+    const bool ok = idx < CNT && ex >= 0 && ex < g.N && ey >= 0 && ey < g.N;
+    // unconditional load from a clamped address keeps all loads in flight; the select zeroes the rest
+    const TC val = (TC)kap[ok ? (long)ey * g.pitch + ex : 0];
+    v[r] = ok ? val : (TC)0;
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx < CNT) sK[idx] = v[r];
+  }
+}
+
 }  // namespace
 }  // namespace irk

@@ -79,8 +79,6 @@ struct Level {
   void* t = nullptr;        // right-hand side (levels >= 1)
   void* x = nullptr;        // pre-smoothed iterate (levels < L-1)
   void* e = nullptr;        // level result / coarse correction (levels >= 1)
-  void* xb = nullptr;       // monolithic cycle: second iterate buffer (levels < L-1)
-  void* r = nullptr;        // monolithic cycle: residual (levels < L-1)
   bool own64 = false;
 };
 
@@ -151,7 +149,8 @@ constexpr int RSTRIDE = kMaxRestart + 2;
 double* res_slot(irk_stepper* st, int which) { return st->dres + (long)which * RSTRIDE; }
 double* sigma_dev(irk_stepper* st) { return st->dres + 4L * RSTRIDE; }
 double* ycoef_dev(irk_stepper* st) { return st->dres + 5L * RSTRIDE; }
-constexpr long DRES_LEN = 6L * RSTRIDE;
+double* dcgs2_dev(irk_stepper* st) { return st->dres + 6L * RSTRIDE; }
+constexpr long DRES_LEN = 6L * RSTRIDE + kDcgs2Res;
 
 // length of the Krylov vectors of the current system
 long sys_len(const irk_stepper* st) { return st->sys < 0 ? st->vlen : st->g.plane; }
@@ -245,10 +244,18 @@ double ortho_bytes(const irk_stepper* st, const OrthoArgs& a) {
   return vec * (nvec + 1 + (ax ? 1 : 0));
 }
 
+// Algorithmic bytes of the two DCGS2 passes over nv finished vectors: the reduction reads Q, u and w;
+// the update reads them and writes u and w.
+double dcgs2_bytes(const irk_stepper* st, int nv, long len, bool update) {
+  const double vec = 8.0 * (double)(len / st->g.plane) * (double)(st->prob->N - 1) * (st->prob->N - 1);
+  return vec * (nv + 2 + (update ? 2 : 0));
+}
+
 int ortho(irk_stepper* st, const OrthoArgs& a, hipStream_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  // only passes over the Krylov vectors are timed (not the setup's per-level norms)
-  if (a.len == sys_len(st)) {
+  // only passes over the Krylov vectors are timed (not the setup's per-level norms); with DCGS2 the timed
+  // family is its reduction and update passes alone
+  if (a.len == sys_len(st) && st->opt.orth != IRK_ORTH_DCGS2) {
     CHK(timer_pair(st, 0, &e0, &e1));
     if (e0) st->timer_bytes += ortho_bytes(st, a);
   }
@@ -527,6 +534,37 @@ void mmg_mixing(const irk_stepper* st, int trans, MMGCoef& c) {
       c.cm[q * kMMGMax + r] = st->ia ? op : id;
       c.ck[q * kMMGMax + r] = st->ia ? id : op;
     }
+  // closed form of the patch-block inverse: with B = Op, adj(I + tau B) = sum_k (-tau)^k N_k and
+  // det(I + tau B) = sum_k c_k (-tau)^k, where N_0 = I, c_k = -tr(B N_{k-1}) / k, N_k = B N_{k-1} + c_k I
+  // (Faddeev-LeVerrier recursion for the characteristic polynomial and adjugate of B)
+  double N[kMMGMax * kMMGMax], BN[kMMGMax * kMMGMax];
+  for (int i = 0; i < kMMGMax * kMMGMax; ++i) N[i] = 0.0;
+  for (int i = 0; i < s; ++i) N[i * kMMGMax + i] = 1.0;
+  for (int i = 0; i < kMMGMax * kMMGMax * kMMGMax; ++i) c.adj[i] = 0.0;
+  for (int i = 0; i <= kMMGMax; ++i) c.det[i] = 0.0;
+  c.det[0] = 1.0;
+  double sign = 1.0;
+  for (int k = 0; k < s; ++k) {
+    for (int i = 0; i < s * kMMGMax; ++i) c.adj[k * kMMGMax * kMMGMax + i] = sign * N[i];
+    // BN = B N_k, c_{k+1} = -tr(BN)/(k+1), N_{k+1} = BN + c_{k+1} I
+    double tr = 0.0;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < s; ++l) acc += st->Op[trans][i * s + l] * N[l * kMMGMax + j];
+        BN[i * kMMGMax + j] = acc;
+      }
+    for (int i = 0; i < s; ++i) tr += BN[i * kMMGMax + i];
+    const double ck = -tr / (k + 1);
+    sign = -sign;
+    c.det[k + 1] = sign * ck;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) N[i * kMMGMax + j] = BN[i * kMMGMax + j] + (i == j ? ck : 0.0);
+  }
+  c.ia = st->ia ? 1 : 0;
+  const double mv = 16.0 * c.m;  // M_vv
+  c.tfac = st->ia ? mv / st->dt : st->dt / mv;
+  c.wfac = st->ia ? 1.0 / st->dt : 1.0 / mv;
 }
 
 // Levels, Chebyshev coefficients (power iteration on C^{-1} Acal per level, both systems) and the coarsest
@@ -571,11 +609,7 @@ int setup_mmg(irk_stepper* st, hipStream_t s) {
       CHK(zalloc(&lev.t));
       CHK(zalloc(&lev.e));
     }
-    if (l < L - 1) {
-      CHK(zalloc(&lev.x));
-      CHK(zalloc(&lev.xb));
-      CHK(zalloc(&lev.r));
-    }
+    if (l < L - 1) CHK(zalloc(&lev.x));
   }
   CHK(check_launch());
   // FP64 power iterations in Krylov workspace (cleared again afterwards)
@@ -699,39 +733,13 @@ int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, double* o
     launch_mmg_coarse(pr, true, true, t, tscale, out, cinv, ml[0].g, ns, s);
     return check_launch();
   }
-  std::vector<void*> xl(L, nullptr);
-  for (int l = 0; l < L - 1; ++l) {
-    const bool f64 = l == 0;
-    const void* tl = f64 ? (const void*)t : ml[l].t;
-    const double* ts = f64 ? tscale : nullptr;
-    void* cur = nullptr;
-    void* prev = nullptr;
-    for (int k = 0; k < cf[l].deg; ++k) {
-      void* o = (cur == ml[l].x) ? ml[l].xb : ml[l].x;
-      launch_mmg_step(pr, f64, false, tl, ts, cur, prev, o, ml[l].kapc, ml[l].g, cf[l], k, s);
-      prev = cur;
-      cur = o;
-    }
-    xl[l] = cur;
-    launch_mmg_residual(pr, f64, tl, ts, cur, ml[l].r, ml[l].kapc, ml[l].g, cf[l], s);
-    launch_mmg_restrict(pr, ml[l].r, ml[l + 1].t, ml[l].g, ml[l + 1].g, ns, s);
-  }
+  for (int l = 0; l < L - 1; ++l)
+    launch_mmg_down(pr, l == 0, l == 0 ? (const void*)t : ml[l].t, l == 0 ? tscale : nullptr, ml[l].x, ml[l + 1].t,
+                    ml[l].kapc, ml[l].g, ml[l + 1].g, cf[l], s);
   launch_mmg_coarse(pr, false, false, ml[L - 1].t, nullptr, ml[L - 1].e, cinv, ml[L - 1].g, ns, s);
-  for (int l = L - 2; l >= 0; --l) {
-    const bool f64 = l == 0;
-    const void* tl = f64 ? (const void*)t : ml[l].t;
-    const double* ts = f64 ? tscale : nullptr;
-    void* cur = xl[l];
-    launch_mmg_prolong(pr, ml[l + 1].e, cur, ml[l].g, ml[l + 1].g, ns, s);
-    void* prev = nullptr;
-    for (int k = 0; k < cf[l].deg; ++k) {
-      const bool last = k + 1 == cf[l].deg;
-      void* o = last ? (f64 ? (void*)out : ml[l].e) : ((cur == ml[l].x) ? ml[l].xb : ml[l].x);
-      launch_mmg_step(pr, f64, last && f64, tl, ts, cur, prev, o, ml[l].kapc, ml[l].g, cf[l], k, s);
-      prev = cur;
-      cur = o;
-    }
-  }
+  for (int l = L - 2; l >= 0; --l)
+    launch_mmg_up(pr, l == 0, l == 0 ? (const void*)t : ml[l].t, l == 0 ? tscale : nullptr, ml[l].x, ml[l + 1].e,
+                  l == 0 ? (void*)out : ml[l].e, ml[l].kapc, ml[l].g, ml[l + 1].g, cf[l], s);
   return check_launch();
 }
 
@@ -838,6 +846,21 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
   double* Vj = st->V + (long)j * n;
   double* Vn = st->V + (long)(j + 1) * n;
   double* Zj = st->Z + (long)j * n;
+  if (st->opt.orth == IRK_ORTH_DCGS2) {
+    // Z_j = P^{-1} u_j (u_j = V_j: the previous direction, projected once), w = Acal Z_j into V_{j+1},
+    // then one reduction and one update pass: V_j <- q_j, V_{j+1} <- the next direction
+    CHK(precondition(st, Vj, nullptr, Zj, trans, s));
+    CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
+    D2Args d{st->V, n, j, Vj, Vn, n, dcgs2_dev(st)};
+    hipEvent_t e0, e1, e2, e3;
+    CHK(timer_pair(st, 0, &e0, &e1));
+    if (e0) st->timer_bytes += dcgs2_bytes(st, j, n, false);
+    launch_dcgs2_dots(d, st->rw, s, e0, e1);
+    CHK(timer_pair(st, 0, &e2, &e3));
+    if (e2) st->timer_bytes += dcgs2_bytes(st, j, n, true);
+    launch_dcgs2_update(d, st->rw, s, e2, e3);
+    return check_launch();
+  }
   CHK(precondition(st, Vj, sig + j, Zj, trans, s));
   CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
   // pass A: h = V^T w, |w|^2
@@ -904,13 +927,147 @@ struct SolveInfo {
   int solves = 0, its_max = 0;
 };
 
+// Least-squares estimate of FGMRES with the (ncol+1) x ncol Hessenberg H (row stride m): Givens QR from
+// scratch; returns |g_ncol| and, if y is given, the solution of R y = g.
+double hessenberg_ls(const std::vector<double>& H, int m, int ncol, double g0, double* y) {
+  std::vector<double> R(H.begin(), H.begin() + (size_t)(ncol + 1) * m), g(ncol + 1, 0.0);
+  g[0] = g0;
+  for (int j = 0; j < ncol; ++j) {
+    const double a = R[(size_t)j * m + j], b = R[(size_t)(j + 1) * m + j];
+    const double r = std::hypot(a, b);
+    const double c = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
+    for (int k = j; k < ncol; ++k) {
+      const double t0 = c * R[(size_t)j * m + k] + sn * R[(size_t)(j + 1) * m + k];
+      const double t1 = -sn * R[(size_t)j * m + k] + c * R[(size_t)(j + 1) * m + k];
+      R[(size_t)j * m + k] = t0;
+      R[(size_t)(j + 1) * m + k] = t1;
+    }
+    const double t0 = c * g[j] + sn * g[j + 1], t1 = -sn * g[j] + c * g[j + 1];
+    g[j] = t0;
+    g[j + 1] = t1;
+  }
+  if (y)
+    for (int i = ncol - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int k = i + 1; k < ncol; ++k) v -= R[(size_t)i * m + k] * y[k];
+      y[i] = v / R[(size_t)i * m + i];
+    }
+  return std::fabs(g[ncol]);
+}
+
+// FGMRES with the delayed CGS2 Arnoldi process. The Hessenberg column of step j is provisional until
+// step j+1 re-orthogonalises and normalises the direction it produced: then the column gains the
+// re-orthogonalisation coefficients and its subdiagonal entry becomes that direction's exact norm
+// (the provisional entry is the norm predicted from the reduction of step j).
+int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s,
+                 double* x) {
+  const int m = st->opt.restart;
+  const long n = sys_len(st);
+  double* h = st->hres;
+  info = SolveInfo{};
+  CHK(norm2(st, f, n, res_slot(st, 0), nullptr, s));
+  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double fnorm = std::sqrt(h[0]);
+  if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
+  if (fnorm == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    return IRK_OK;
+  }
+  if (use_guess) {
+    CHK(apply_op(st, x, st->V, f, trans, s));
+  } else {
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    HIPCHK(hipMemcpyAsync(st->V, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  CHK(norm2(st, st->V, n, res_slot(st, 0), nullptr, s));
+  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double beta = std::sqrt(h[0]);
+  const double target = st->opt.rtol * fnorm;
+  if (beta <= target) {
+    info.rel = beta / fnorm;
+    return IRK_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), y(m);
+  while (true) {
+    std::fill(H.begin(), H.end(), 0.0);
+    double g0 = beta;
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+      CHK(run_arnoldi(st, j, trans, s));
+      const int cnt = 2 * j + 3;
+      HIPCHK(hipMemcpyAsync(h, dcgs2_dev(st), (cnt + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool finite = true;
+      for (int i = 0; i < cnt + 5; ++i) finite = finite && std::isfinite(h[i]);
+      if (!finite) return fail(IRK_EBREAKDOWN, "non-finite Hessenberg entry in FGMRES");
+      const double* a = h;
+      const double* sw = h + j;
+      const double bj = h[cnt], hj = h[cnt + 2], nu = h[cnt + 3];
+      if (h[cnt + 4] != 0.0) {
+        // the direction u_j vanished: the Krylov space is invariant and column j-1 is exact
+        if (j == 0) return fail(IRK_EBREAKDOWN, "zero initial direction in FGMRES");
+        for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += a[i];
+        H[(size_t)j * m + (j - 1)] = 0.0;
+        break;
+      }
+      if (j == 0) {
+        g0 = bj;
+      } else {
+        for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += a[i];
+        H[(size_t)j * m + (j - 1)] = bj;
+      }
+      for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = sw[i];
+      H[(size_t)j * m + j] = hj;
+      H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(nu, 0.0));
+      info.its++;
+      jdone = j + 1;
+      const double est = hessenberg_ls(H, m, jdone, g0, nullptr);
+      if (est <= target || H[(size_t)(j + 1) * m + j] <= 1e-300 * std::fabs(hj)) break;
+      if (info.its >= st->opt.max_it) break;
+    }
+    if (jdone > 0) {
+      hessenberg_ls(H, m, jdone, g0, y.data());
+      std::copy(y.begin(), y.begin() + jdone, h);
+      HIPCHK(hipMemcpyAsync(ycoef_dev(st), h, jdone * sizeof(double), hipMemcpyHostToDevice, s));
+      OrthoArgs ax = ortho_base();
+      ax.V = st->Z;
+      ax.vstride = n;
+      ax.nv = jdone;
+      ax.w = x;
+      ax.len = n;
+      ax.coef = ycoef_dev(st);
+      ax.coef_sign = -1.0;
+      ax.result = res_slot(st, 3);
+      CHK(ortho(st, ax, s));
+    }
+    CHK(apply_op(st, x, st->V, f, trans, s));
+    CHK(norm2(st, st->V, n, res_slot(st, 0), nullptr, s));
+    HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    beta = std::sqrt(h[0]);
+    info.rel = beta / fnorm;
+    if (!std::isfinite(beta)) return fail(IRK_EBREAKDOWN, "non-finite residual in FGMRES");
+    if (beta <= target) return IRK_OK;
+    if (info.its >= st->opt.max_it) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "FGMRES reached max_it = %d with relative residual %.3e > rtol %.3e", st->opt.max_it,
+               info.rel, st->opt.rtol);
+      return fail(IRK_ENOCONV, buf);
+    }
+    info.restarts++;
+  }
+}
+
 // Solve Acal x = f (padded planes) for the current system; x defaults to st->k. If use_guess, x holds
 // the initial guess.
 int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s,
            double* x = nullptr) {
+  if (!x) x = st->k;
+  if (st->opt.orth == IRK_ORTH_DCGS2) return fgmres_dcgs2(st, f, trans, use_guess, info, s, x);
   const int m = st->opt.restart;
   const long n = sys_len(st);
-  if (!x) x = st->k;
   double* sig = sigma_dev(st);
   double* h = st->hres;
   info = SolveInfo{};
@@ -1190,7 +1347,7 @@ void irk_options_default(irk_options* o) {
   o->cheb_hi = 1.1;
   o->power_its = 15;
   o->mg_precision = IRK_F64;
-  o->orth = IRK_ORTH_CGS2;
+  o->orth = IRK_ORTH_DCGS2;
   o->initial_guess = IRK_GUESS_ZERO;
   o->use_graphs = 1;
   o->splitting = IRK_SPLIT_AI;
@@ -1298,8 +1455,6 @@ void irk_stepper_destroy(irk_stepper* st) {
     if (L.own64) dev_free(L.kap64);
     dev_free(L.t);
     dev_free(L.x);
-    dev_free(L.xb);
-    dev_free(L.r);
     dev_free(L.e);
   }
   dev_free(st->mcinv[0]);
@@ -1347,7 +1502,8 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   if (!(o.cheb_lo > 0) || !(o.cheb_hi > o.cheb_lo)) return fail(IRK_EINVAL, "need 0 < cheb_lo < cheb_hi");
   if (o.power_its < 1 || o.power_its > 1000) return fail(IRK_EINVAL, "power_its must be 1..1000");
   if (o.mg_precision < IRK_F64 || o.mg_precision > IRK_BF16) return fail(IRK_EINVAL, "unknown mg_precision");
-  if (o.orth != IRK_ORTH_CGS2 && o.orth != IRK_ORTH_CGS_SELECTIVE) return fail(IRK_EINVAL, "unknown orth");
+  if (o.orth != IRK_ORTH_CGS2 && o.orth != IRK_ORTH_CGS_SELECTIVE && o.orth != IRK_ORTH_DCGS2)
+    return fail(IRK_EINVAL, "unknown orth");
   if (o.initial_guess != IRK_GUESS_ZERO && o.initial_guess != IRK_GUESS_PREV)
     return fail(IRK_EINVAL, "unknown initial_guess");
   if (o.mg_coarse_n < 1) return fail(IRK_EINVAL, "mg_coarse_n must be >= 1");

@@ -169,18 +169,22 @@ def test_selective_reorthogonalisation_and_prev_guess():
 
 
 def test_dirk_gs_lower_with_exact_blocks_converges_in_one_iteration():
-    # lower-triangular A: P_L equals the stage operator; with one level the V-cycle is an exact solve
+    # lower-triangular A: P_L equals the stage operator; with one level the V-cycle is an exact solve, so
+    # one Arnoldi step solves the system. With CGS2 the residual estimate shows it at once; DCGS2 predicts
+    # the next direction's norm by subtraction (|w|^2 - |h|^2, exact only down to sqrt(eps)|w|) and sees it
+    # one step later, when that direction is re-orthogonalised and measured.
     N, dt = 8, 1e-2
     kap = synth.grf_kappa(N, 3)
-    _, stp = make(N, kap, P.tableaux.alexander(), dt, precond=P.PC_GS_LOWER, rtol=1e-12)
-    assert stp.levels == 1
     f = synth.random_stage_block(N, 3, 2).ravel()
-    _, stats = stp.solve_stages(dev(f))
-    assert stats["fgmres_its_total"] == 1
-    # s = 1 (backward Euler) with P_D likewise
-    _, stp1 = make(N, kap, P.tableaux.radau_iia(1), dt, precond=P.PC_JACOBI, rtol=1e-12)
-    _, stats = stp1.solve_stages(dev(f[: (N - 1) ** 2]))
-    assert stats["fgmres_its_total"] == 1
+    for orth, its in ((P.ORTH_CGS2, 1), (P.ORTH_DCGS2, 2)):
+        _, stp = make(N, kap, P.tableaux.alexander(), dt, precond=P.PC_GS_LOWER, rtol=1e-12, orth=orth)
+        assert stp.levels == 1
+        _, stats = stp.solve_stages(dev(f))
+        assert 1 <= stats["fgmres_its_total"] <= its
+        # s = 1 (backward Euler) with P_D likewise
+        _, stp1 = make(N, kap, P.tableaux.radau_iia(1), dt, precond=P.PC_JACOBI, rtol=1e-12, orth=orth)
+        _, stats = stp1.solve_stages(dev(f[: (N - 1) ** 2]))
+        assert 1 <= stats["fgmres_its_total"] <= its
 
 
 def test_iterations_grow_with_stages_and_gs_beats_jacobi():
@@ -346,3 +350,62 @@ def test_dirk_rejects_full_tableau_and_ia():
         with pytest.raises(P.IrkError) as e:
             P.Stepper(prob, tab, 1e-3, stage_type=P.STAGE_DIRK, **opts)
         assert e.value.code == P.IRK_EINVAL
+
+
+# ---------------------------------------------------------------- delayed CGS2 Arnoldi process
+
+
+@pytest.mark.parametrize("pc,splitting,restart", [(P.PC_GS_LOWER, P.SPLIT_AI, 30), (P.PC_MONOLITHIC, P.SPLIT_AI, 30),
+                                                  (P.PC_RANA_LD, P.SPLIT_IA, 30), (P.PC_GS_LOWER, P.SPLIT_AI, 3)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_dcgs2_solve_stages_matches_direct(pc, splitting, restart, transpose):
+    N, dt = 64, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    A = OT.radau_iia(3)["A"]
+    _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=pc, splitting=splitting, rtol=1e-12,
+                  orth=P.ORTH_DCGS2, restart=restart)
+    f = synth.random_stage_block(N, 3, 25).ravel()
+    x, stats = stp.solve_stages(dev(f), transpose=transpose)
+    Acal = step.coupled_matrix(M, K, A, dt) if splitting == P.SPLIT_AI else step.coupled_matrix_ia(M, K, A, dt)
+    if transpose:
+        Acal = Acal.T.tocsc()
+    ref = spla.spsolve(Acal, f)
+    assert np.linalg.norm(Acal @ host(x) - f) <= 1.01e-12 * np.linalg.norm(f)
+    assert rel(host(x), ref) < 1e-9
+    if restart == 3:
+        assert stats["restarts_total"] >= 1
+
+
+def test_dcgs2_iterations_match_cgs2():
+    # the delayed form builds the same Krylov space: the iteration counts agree with CGS2 (up to one)
+    N, dt = 128, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    its, us = {}, {}
+    for orth in (P.ORTH_CGS2, P.ORTH_DCGS2):
+        _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, rtol=1e-10, orth=orth)
+        u = dev(u0)
+        _, st = stp.advance(u, 3)
+        its[orth] = st["fgmres_its_total"]
+        us[orth] = host(u)
+    assert abs(its[P.ORTH_DCGS2] - its[P.ORTH_CGS2]) <= 3
+    assert rel(us[P.ORTH_DCGS2], us[P.ORTH_CGS2]) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [P.F64, P.F32])
+def test_dcgs2_graph_replay_matches_eager_bitwise(prec):
+    N, dt, nsteps = 64, 1e-3, 3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    outs = []
+    for g in (0, 1):
+        _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, use_graphs=g, mg_precision=prec, restart=6,
+                      orth=P.ORTH_DCGS2)
+        u = dev(u0)
+        stp.advance(u, nsteps)
+        u2 = dev(u0)
+        stp.advance(u2, nsteps)
+        outs.append((host(u), host(u2)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[1][0], outs[1][1])
