@@ -23,6 +23,10 @@
 namespace irk {
 namespace {
 
+// threads per block of the level kernels: a tile phase has up to (TX + 2H)(TY + 2H) nodes, and 16 waves per
+// block shorten each phase of these latency-bound kernels (measured: 1024 threads 9% faster than 256)
+constexpr int NT = 1024;
+
 // B x and D at LDS node (li, lj); X has row length RX, K (element field) row length KX = RX + 1
 template <typename TC, int RX, int KX>
 __device__ __forceinline__ void bx_d(const TC* X, const TC* K, int li, int lj, TC m, TC alpha, TC& Bx, TC& D) {
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
     }
     CoupleLoad<TC, RX, RY> w;
     if (COUPLE) w.load(cp, ox, oy, g);
-    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+    load_kappa_tile<TC, TC, KX, KY, NT>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
       const int idx = threadIdx.x + r * NT;
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
     }
     CoupleLoad<TC, RX, RY> w;
     if (COUPLE) w.load(cp, ox, oy, g);
-    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+    load_kappa_tile<TC, TC, KX, KY, NT>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
       const int idx = threadIdx.x + r * NT;

@@ -18,6 +18,9 @@
 namespace irk {
 namespace {
 
+// threads per block of the fused level kernels (512: eight waves share a tile's phases; 1024 would cap
+// the registers of the s-plane kernels and spill)
+constexpr int NT = 512;
 constexpr int MX = 64, MY = 4;  // thread block of the nodal kernels
 
 __device__ __forceinline__ bool mmg_node(const Geom& g, int& i, int& j) {
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(NT) void mmg_down_kernel(const TT* __restrict__ t, 
         const TC val = ld<TC>(t + q * g.plane + (ok ? (long)j * g.pitch + i : 0));
         tv[q][r] = ok ? val * ts : (TC)0;
       }
-    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+    load_kappa_tile<TC, TC, KX, KY, NT>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int q = 0; q < S; ++q)
 #pragma unroll
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(NT) void mmg_up_kernel(const TT* __restrict__ t, co
         tv[q][r] = ok ? a : (TC)0;
         xv[q][r] = ok ? b : (TC)0;
       }
-    load_kappa_tile<TC, TC, KX, KY>(sK, kap, ox, oy, g);
+    load_kappa_tile<TC, TC, KX, KY, NT>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int q = 0; q < S; ++q)
 #pragma unroll

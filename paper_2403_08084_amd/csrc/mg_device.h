@@ -8,8 +8,6 @@
 namespace irk {
 namespace {
 
-constexpr int NT = 256;
-
 __device__ __forceinline__ float bf2f(uint16_t u) { return __uint_as_float(((uint32_t)u) << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
   // round to nearest even (inputs are finite)
@@ -46,7 +44,7 @@ __device__ __forceinline__ TC prolong_at(const TS* __restrict__ e, int pc, int i
 
 // Tile loads are staged through registers with fully unrolled loops, so every
 // thread has all of its global loads in flight before the first LDS store.
-template <typename TC, typename TK, int KX, int KY>
+template <typename TC, typename TK, int KX, int KY, int NT>
 __device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ kap, int ox, int oy, const Geom& g) {
   constexpr int CNT = KX * KY, NL = (CNT + NT - 1) / NT;
   TC v[NL];
