@@ -318,13 +318,16 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
 // Coarsest level: out = Binv * t on the n = (N-1)^2 <= 1024 interior nodes. One wavefront per
 // row; each lane issues all of its (at most 16) coalesced row loads and right-hand-side loads
 // before accumulating, then a fixed-order wavefront reduction.
+// Blocks of NTC = 256 threads (four rows each): spreading the rows over many CUs matters more here than
+// the level kernels' large blocks.
+constexpr int NTC = 256;
 template <typename TI, typename TO, typename TC>
-__global__ __launch_bounds__(NT) void mg_coarse_kernel(const TI* __restrict__ t, const double* __restrict__ tscale,
-                                                       TO* __restrict__ out, const TC* __restrict__ Binv, Geom g) {
+__global__ __launch_bounds__(NTC) void mg_coarse_kernel(const TI* __restrict__ t, const double* __restrict__ tscale,
+                                                        TO* __restrict__ out, const TC* __restrict__ Binv, Geom g) {
   const int m = g.N - 1;
   const int n = m * m;
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int row = blockIdx.x * (NTC / 64) + (threadIdx.x >> 6);
   if (row >= n) return;
   const TC* r = Binv + (long)row * n;
   constexpr int U = kMaxCoarse / 64;
@@ -455,18 +458,18 @@ void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale,
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
                       hipStream_t st) {
   const int n = (g.N - 1) * (g.N - 1);
-  const dim3 grid((n + NT / 64 - 1) / (NT / 64));
+  const dim3 grid((n + NTC / 64 - 1) / (NTC / 64));
   if (prec == 0) {
-    mg_coarse_kernel<double, double, double><<<grid, NT, 0, st>>>((const double*)t, tscale, (double*)out,
+    mg_coarse_kernel<double, double, double><<<grid, NTC, 0, st>>>((const double*)t, tscale, (double*)out,
                                                                  (const double*)Binv, g);
   } else if (io_is_f64) {
-    mg_coarse_kernel<double, double, float><<<grid, NT, 0, st>>>((const double*)t, tscale, (double*)out,
+    mg_coarse_kernel<double, double, float><<<grid, NTC, 0, st>>>((const double*)t, tscale, (double*)out,
                                                                 (const float*)Binv, g);
   } else if (prec == 1) {
-    mg_coarse_kernel<float, float, float><<<grid, NT, 0, st>>>((const float*)t, tscale, (float*)out,
+    mg_coarse_kernel<float, float, float><<<grid, NTC, 0, st>>>((const float*)t, tscale, (float*)out,
                                                               (const float*)Binv, g);
   } else {
-    mg_coarse_kernel<bf16, bf16, float><<<grid, NT, 0, st>>>((const bf16*)t, tscale, (bf16*)out, (const float*)Binv,
+    mg_coarse_kernel<bf16, bf16, float><<<grid, NTC, 0, st>>>((const bf16*)t, tscale, (bf16*)out, (const float*)Binv,
                                                             g);
   }
 }
