@@ -10,6 +10,19 @@ Main objects
   Problem(N, kappa)                the Q1 grid and per-element diffusivity
   Stepper(problem, tableau, dt, ...)  a tableau, time step and solver options
   IrkSolve                         torch.autograd.Function: u_N(u_0, log kappa)
+
+Stepper options (fields of irk_options; defaults from irk_options_default):
+  precond       PC_GS_LOWER (block lower Gauss-Seidel), PC_JACOBI, PC_GS_UPPER, PC_RANA_LD, PC_MONOLITHIC
+  splitting     SPLIT_AI (stage derivatives k) or SPLIT_IA (w = (A (x) I) k)
+  stage_type    STAGE_COUPLED or STAGE_DIRK (stage-by-stage solves, lower-triangular A)
+  mg_precision  F64, F32 or BF16 storage of the multigrid vectors (FGMRES stays FP64)
+  orth          ORTH_DCGS2 (one reduction per Arnoldi step), ORTH_CGS2, ORTH_CGS_SELECTIVE
+  rtol, restart, max_it, mg_coarse_n, cheb_degree, cheb_lo, cheb_hi, power_its, initial_guess, use_graphs
+
+Example (1024^2, Radau IIA(3), mixed precision, monolithic multigrid):
+  prob = Problem(1024, kappa_dev)
+  stp = Stepper(prob, tableaux.radau_iia(3), 1e-3, mg_precision=F32, precond=PC_MONOLITHIC)
+  rc, stats = stp.advance(u_dev, 20)
 """
 from __future__ import annotations
 
