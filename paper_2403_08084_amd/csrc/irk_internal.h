@@ -45,6 +45,16 @@ inline Geom make_geom(int N) {
   return g;
 }
 
+// XCD-aware tile order. Workgroups of a launch are dealt round-robin to the chip's 8 XCDs, each with its own L2;
+// tile = xcd_tile(linear block id, block count) gives every XCD a contiguous range of tiles, so neighbouring tiles
+// (which read each other's halo rows) share one L2. A bijection of [0, nb) for any nb.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // s x s coefficient matrix passed by value to kernels
 struct Coefs {
   double a[kMaxStages * kMaxStages];

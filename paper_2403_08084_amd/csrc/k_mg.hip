@@ -121,7 +121,10 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
   __shared__ TC sA[COUPLE ? (RX + 2) * (RY + 2) : RX * RY];  // also stages the coupling field
   __shared__ TC sB[RX * RY];
   const int N = g.N;
-  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  // tiles on a 1-D grid in XCD-aware order: neighbouring tiles (shared halos) run on the same XCD
+  const int ntx = (g.N - 1 + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i0 = 1 + (tile % ntx) * TX, j0 = 1 + (tile / ntx) * TY;
   const int ox = i0 - H, oy = j0 - H;
   const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)((tscale ? *tscale : 1.0) * cp.vmul);
 
@@ -233,7 +236,10 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
   __shared__ TC sA[RX * RY];
   __shared__ TC sB[COUPLE ? (RX + 2) * (RY + 2) : RX * RY];  // also stages the coupling field
   const int N = g.N;
-  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  // tiles on a 1-D grid in XCD-aware order: neighbouring tiles (shared halos) run on the same XCD
+  const int ntx = (g.N - 1 + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i0 = 1 + (tile % ntx) * TX, j0 = 1 + (tile / ntx) * TY;
   const int ox = i0 - H, oy = j0 - H;
   const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)((tscale ? *tscale : 1.0) * cp.vmul);
 
@@ -362,7 +368,7 @@ constexpr int kSmallLevel = 512;
 template <typename TV, typename TS, typename TC, bool CP, int TX, int TY>
 void down_tiles(const TV* tt, const double* tscale, TS* xx, TS* cc, const TC* kk, Geom g, Geom gc, const MGCoef& c,
                 const Couple& cp, hipStream_t st) {
-  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
   switch (c.deg) {
     case 1: mg_down_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
     case 2: mg_down_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
@@ -391,7 +397,7 @@ void down_t(const void* t, const double* tscale, void* x, void* tc, const void* 
 template <typename TV, typename TS, typename TC, bool CP, int TX, int TY>
 void up_tiles(const TV* tt, const double* tscale, const TS* xx, const TS* ee, TV* oo, const TC* kk, Geom g, Geom gc,
               const MGCoef& c, const Couple& cp, hipStream_t st) {
-  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
   switch (c.deg) {
     case 1: mg_up_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
     case 2: mg_up_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;

@@ -235,7 +235,10 @@ __global__ __launch_bounds__(NT) void mmg_down_kernel(const TT* __restrict__ t, 
   __shared__ TC sA[S * PA];
   __shared__ TC sB[S * PA];
   const int N = g.N;
-  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  // tiles on a 1-D grid in XCD-aware order: neighbouring tiles (shared halos) run on the same XCD
+  const int ntx = (g.N - 1 + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i0 = 1 + (tile % ntx) * TX, j0 = 1 + (tile / ntx) * TY;
   const int ox = i0 - H, oy = j0 - H;
   const TC ts = tscale ? (TC)(*tscale) : (TC)1;
   {
@@ -369,7 +372,10 @@ __global__ __launch_bounds__(NT) void mmg_up_kernel(const TT* __restrict__ t, co
   __shared__ TC sA[S * PA];
   __shared__ TC sB[S * PA];
   const int N = g.N;
-  const int i0 = 1 + blockIdx.x * TX, j0 = 1 + blockIdx.y * TY;
+  // tiles on a 1-D grid in XCD-aware order: neighbouring tiles (shared halos) run on the same XCD
+  const int ntx = (g.N - 1 + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i0 = 1 + (tile % ntx) * TX, j0 = 1 + (tile / ntx) * TY;
   const int ox = i0 - H, oy = j0 - H;
   const TC ts = tscale ? (TC)(*tscale) : (TC)1;
   {
@@ -536,7 +542,7 @@ template <typename TT, typename TS, typename TC, int S, int DEG, bool SMALL>
 void down_k(const void* t, const double* ts, void* x, void* tc, const void* kap, Geom g, Geom gc, const MMGCoef& c,
             hipStream_t st) {
   constexpr int TX = MTile<TC, S, SMALL>::TX, TY = MTile<TC, S, SMALL>::TY;
-  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
   mmg_down_kernel<TT, TS, TC, S, DEG, TX, TY><<<grid, NT, 0, st>>>((const TT*)t, ts, (TS*)x, (TS*)tc, (const TC*)kap,
                                                                    g, gc, c);
 }
@@ -545,7 +551,7 @@ template <typename TT, typename TS, typename TO, typename TC, int S, int DEG, bo
 void up_k(const void* t, const double* ts, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
           const MMGCoef& c, hipStream_t st) {
   constexpr int TX = MTile<TC, S, SMALL>::TX, TY = MTile<TC, S, SMALL>::TY;
-  const dim3 grid((g.N - 1 + TX - 1) / TX, (g.N - 1 + TY - 1) / TY);
+  const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
   mmg_up_kernel<TT, TS, TO, TC, S, DEG, TX, TY><<<grid, NT, 0, st>>>((const TT*)t, ts, (const TS*)x, (const TS*)e,
                                                                      (TO*)out, (const TC*)kap, g, gc, c);
 }

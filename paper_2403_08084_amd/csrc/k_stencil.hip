@@ -143,41 +143,88 @@ __global__ void coarsen_kappa_kernel(const double* __restrict__ f, double* __res
 
 // ------------------------------------------------------------------ stencils
 
+// Stage operator, register-blocked: each thread owns RB consecutive nodes of one column, so the three rows
+// of every 9-point stencil and the element diffusivities are loaded once per column segment
+// ((RB + 2) * 3 values per plane and 2 (RB + 1) diffusivities for RB nodes); tiles in XCD-aware order.
+constexpr int RB = 4;
+
 template <int S, bool IA>
 __global__ __launch_bounds__(BX* BY) void stage_operator_kernel(const double* __restrict__ x, double* __restrict__ y,
                                                                 const double* __restrict__ f,
                                                                 const double* __restrict__ kap, Geom g, Coefs a,
                                                                 double dt) {
-  int i, j;
-  if (!node_of_thread(g, i, j)) return;
-  const int P = g.pitch;
-  const long p = (long)j * P + i;
+  const int N = g.N, P = g.pitch;
+  const int ntx = (N - 1 + BX - 1) / BX;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int i = 1 + (t % ntx) * BX + threadIdx.x;
+  const int j0 = 1 + (t / ntx) * (BY * RB) + threadIdx.y * RB;
+  if (i > N - 1 || j0 > N - 1) return;
   const double m = g.h * g.h / 36.0;
-  const Kap k = load_kap(kap, p, P);
-  double Kx[S], Mx[S];
+  // element rows j0-1 .. j0+RB-1 and node rows j0-1 .. j0+RB, clamped to the array (values past the
+  // last interior row are loaded but not used)
+  double kw[RB + 1], ke[RB + 1];
+#pragma unroll
+  for (int r = 0; r <= RB; ++r) {
+    const int er = min(j0 - 1 + r, N - 1);
+    kw[r] = kap[(long)er * P + i - 1];
+    ke[r] = kap[(long)er * P + i];
+  }
+  double Kx[S][RB], Mx[S][RB];
 #pragma unroll
   for (int q = 0; q < S; ++q) {
-    const Nb v = load_nb(x + q * g.plane, p, P);
-    Kx[q] = stiff(v, k);
-    Mx[q] = mass(v, m);
+    double xw[RB + 2], xc[RB + 2], xe[RB + 2];
+#pragma unroll
+    for (int r = 0; r < RB + 2; ++r) {
+      const int nr = min(j0 - 1 + r, N);
+      const long pr = q * g.plane + (long)nr * P + i;
+      xw[r] = x[pr - 1];
+      xc[r] = x[pr];
+      xe[r] = x[pr + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      Kap k;
+      k.sw = kw[r];
+      k.se = ke[r];
+      k.nw = kw[r + 1];
+      k.ne = ke[r + 1];
+      Nb v;
+      v.c = xc[r + 1];
+      v.e = xe[r + 1];
+      v.w = xw[r + 1];
+      v.n = xc[r + 2];
+      v.s = xc[r];
+      v.ne = xe[r + 2];
+      v.nw = xw[r + 2];
+      v.se = xe[r];
+      v.sw = xw[r];
+      Kx[q][r] = stiff(v, k);
+      Mx[q][r] = mass(v, m);
+    }
   }
 #pragma unroll
-  for (int r = 0; r < S; ++r) {
-    double acc = 0.0, val;
-    if (IA) {
-      // (A^{-1} (x) M + dt I (x) K) x: stage mixing on the mass term
+  for (int r = 0; r < RB; ++r) {
+    const int j = j0 + r;
+    if (j > N - 1) break;
+    const long p = (long)j * P + i;
 #pragma unroll
-      for (int q = 0; q < S; ++q) acc += a.a[r * kMaxStages + q] * Mx[q];
-      val = acc + dt * Kx[r];
-    } else {
+    for (int qo = 0; qo < S; ++qo) {
+      double acc = 0.0, val;
+      if (IA) {
+        // (A^{-1} (x) M + dt I (x) K) x: stage mixing on the mass term
 #pragma unroll
-      for (int q = 0; q < S; ++q) acc += a.a[r * kMaxStages + q] * Kx[q];
-      val = Mx[r] + dt * acc;
+        for (int q = 0; q < S; ++q) acc += a.a[qo * kMaxStages + q] * Mx[q][r];
+        val = acc + dt * Kx[qo][r];
+      } else {
+#pragma unroll
+        for (int q = 0; q < S; ++q) acc += a.a[qo * kMaxStages + q] * Kx[q][r];
+        val = Mx[qo][r] + dt * acc;
+      }
+      if (f)
+        y[qo * g.plane + p] = f[qo * g.plane + p] - val;
+      else
+        y[qo * g.plane + p] = val;
     }
-    if (f)
-      y[r * g.plane + p] = f[r * g.plane + p] - val;
-    else
-      y[r * g.plane + p] = val;
   }
 }
 
@@ -364,7 +411,8 @@ void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, 
 template <bool IA>
 void stage_operator_t(const double* x, double* y, const double* f, const double* kappa, Geom g, int s, const Coefs& a,
                       double dt, hipStream_t st) {
-  const dim3 grid = stencil_grid(g), blk(BX, BY);
+  const int ntx = (g.N - 1 + BX - 1) / BX, nty = (g.N - 1 + BY * RB - 1) / (BY * RB);
+  const dim3 grid(ntx * nty), blk(BX, BY);
   switch (s) {
     case 1: stage_operator_kernel<1, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
     case 2: stage_operator_kernel<2, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
