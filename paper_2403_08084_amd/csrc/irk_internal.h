@@ -147,11 +147,13 @@ struct Couple {
 // prec: 0 = FP64 storage/compute, 1 = FP32, 2 = BF16 storage / FP32 compute.
 // DOWN: pre-smooth from zero on the fine level, write x, restrict the residual into tc (coarse).
 // t_is_f64: t is the FP64 Krylov vector (scaled by the device scalar *tscale; null = 1) instead of level storage.
-void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, const void* kappa,
-                    Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
-// UP: x0 = x + P e, post-smooth, write out (FP64 if out_is_f64).
-void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
-                  const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
+// tout (optional, compute type, finest level): receives the right-hand side the smoother used (scaled, coupled).
+void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, void* tout,
+                    const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
+// UP: x0 = x + P e, post-smooth, write out. finest: t is the compute-type right-hand side stored by DOWN and out
+// is the FP64 result; otherwise t and out are level storage.
+void launch_mg_up(int prec, bool finest, const void* t, const void* x, const void* e, void* out, const void* kappa,
+                  Geom g, Geom gc, const MGCoef& c, hipStream_t st);
 // coarsest level: out = Binv * t on the interior nodes
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
                       hipStream_t st);

@@ -109,10 +109,13 @@ __device__ __forceinline__ void couple_apply(TC* sT, const TC* sW, const TC* sK,
   }
 }
 
+// tout (optional): the level's right-hand side as the smoother sees it (scaled, coupling applied), stored on the
+// tile in the compute type so that the UP kernel of the same V-cycle reads it instead of recomputing it
 template <typename TV, typename TS, typename TC, int DEG, int TX, int TY, bool COUPLE>
 __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, const double* __restrict__ tscale, TS* __restrict__ xout,
-                                                     TS* __restrict__ tc, const TC* __restrict__ kap, Geom g, Geom gc,
-                                                     MGCoef cf, Couple cp) {
+                                                     TS* __restrict__ tc, TC* __restrict__ tout,
+                                                     const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf,
+                                                     Couple cp) {
   constexpr int H = DEG + 1;
   constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int KX = RX + 1, KY = RY + 1;
@@ -186,11 +189,14 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
     cur = prv;
     prv = tmp;
   }
-  // smoothed x on the tile
+  // smoothed x (and the right-hand side) on the tile
   for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
     const int lj = H + idx / TX, li = H + idx % TX;
     const int i = ox + li, j = oy + lj;
-    if (interior(i, j, N)) st(xout + (long)j * g.pitch + i, cur[lj * RX + li]);
+    if (interior(i, j, N)) {
+      st(xout + (long)j * g.pitch + i, cur[lj * RX + li]);
+      if (tout) tout[(long)j * g.pitch + i] = sT[lj * RX + li];
+    }
   }
   // residual on the tile plus one node
   {
@@ -224,24 +230,25 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
   }
 }
 
-template <typename TV, typename TS, typename TC, int DEG, int TX, int TY, bool COUPLE>
-__global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, const double* __restrict__ tscale, const TS* __restrict__ x,
-                                                   const TS* __restrict__ e, TV* __restrict__ out,
-                                                   const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf, Couple cp) {
+// t: the level's right-hand side (finest level: the one the DOWN kernel stored, already scaled and coupled)
+template <typename TT, typename TS, typename TO, typename TC, int DEG, int TX, int TY>
+__global__ __launch_bounds__(NT) void mg_up_kernel(const TT* __restrict__ t, const TS* __restrict__ x,
+                                                   const TS* __restrict__ e, TO* __restrict__ out,
+                                                   const TC* __restrict__ kap, Geom g, Geom gc, MGCoef cf) {
   constexpr int H = DEG;
   constexpr int RX = TX + 2 * H, RY = TY + 2 * H;
   constexpr int KX = RX + 1, KY = RY + 1;
   __shared__ TC sK[KX * KY];
   __shared__ TC sT[RX * RY];
   __shared__ TC sA[RX * RY];
-  __shared__ TC sB[COUPLE ? (RX + 2) * (RY + 2) : RX * RY];  // also stages the coupling field
+  __shared__ TC sB[RX * RY];
   const int N = g.N;
   // tiles on a 1-D grid in XCD-aware order: neighbouring tiles (shared halos) run on the same XCD
   const int ntx = (g.N - 1 + TX - 1) / TX;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int i0 = 1 + (tile % ntx) * TX, j0 = 1 + (tile / ntx) * TY;
   const int ox = i0 - H, oy = j0 - H;
-  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, ts = (TC)((tscale ? *tscale : 1.0) * cp.vmul);
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha;
 
   {
     constexpr int CNT = RX * RY, NL = (CNT + NT - 1) / NT;
@@ -254,13 +261,11 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
       const bool ok = idx < CNT && interior(i, j, N);
       const int ic = ok ? i : 1, jc = ok ? j : 1;
       const long p = (long)jc * g.pitch + ic;
-      const TC a = ld<TC>(t + p) * ts;
+      const TC a = ld<TC>(t + p);
       const TC b = ld<TC>(x + p) + prolong_at<TS, TC>(e, gc.pitch, ic, jc);
       tv[r] = ok ? a : (TC)0;
       xv[r] = ok ? b : (TC)0;
     }
-    CoupleLoad<TC, RX, RY> w;
-    if (COUPLE) w.load(cp, ox, oy, g);
     load_kappa_tile<TC, TC, KX, KY, NT>(sK, kap, ox, oy, g);
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
@@ -270,13 +275,8 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TV* __restrict__ t, con
         sA[idx] = xv[r];
       }
     }
-    if (COUPLE) w.store(sB);
   }
   __syncthreads();
-  if (COUPLE) {
-    couple_apply<TC, RX, RY, KX>(sT, sB, sK, cp, ox, oy, g);
-    __syncthreads();
-  }
   // first step from the corrected x0: x1 = x0 + c0 D^{-1} (t - B x0), written on the whole
   // inner region (zero outside the domain); the region's edge ring of sB is never read again
   {
@@ -366,98 +366,95 @@ constexpr int TXD = 64, TYD = 16, TXS = 32, TYS = 8;
 constexpr int kSmallLevel = 512;
 
 template <typename TV, typename TS, typename TC, bool CP, int TX, int TY>
-void down_tiles(const TV* tt, const double* tscale, TS* xx, TS* cc, const TC* kk, Geom g, Geom gc, const MGCoef& c,
-                const Couple& cp, hipStream_t st) {
+void down_tiles(const TV* tt, const double* tscale, TS* xx, TS* cc, TC* to, const TC* kk, Geom g, Geom gc,
+                const MGCoef& c, const Couple& cp, hipStream_t st) {
   const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
   switch (c.deg) {
-    case 1: mg_down_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
-    case 2: mg_down_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
-    default: mg_down_kernel<TV, TS, TC, 3, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, kk, g, gc, c, cp); break;
+    case 1:
+      mg_down_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      break;
+    case 2:
+      mg_down_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      break;
+    default:
+      mg_down_kernel<TV, TS, TC, 3, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      break;
   }
 }
 
 template <typename TV, typename TS, typename TC, bool CP>
-void down_launch(const TV* tt, const double* tscale, TS* xx, TS* cc, const TC* kk, Geom g, Geom gc, const MGCoef& c,
-                 const Couple& cp, hipStream_t st) {
+void down_launch(const TV* tt, const double* tscale, TS* xx, TS* cc, TC* to, const TC* kk, Geom g, Geom gc,
+                 const MGCoef& c, const Couple& cp, hipStream_t st) {
   if (g.N < kSmallLevel)
-    down_tiles<TV, TS, TC, CP, TXS, TYS>(tt, tscale, xx, cc, kk, g, gc, c, cp, st);
+    down_tiles<TV, TS, TC, CP, TXS, TYS>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
   else
-    down_tiles<TV, TS, TC, CP, TXD, TYD>(tt, tscale, xx, cc, kk, g, gc, c, cp, st);
+    down_tiles<TV, TS, TC, CP, TXD, TYD>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
 }
 
 template <typename TV, typename TS, typename TC>
-void down_t(const void* t, const double* tscale, void* x, void* tc, const void* kap, Geom g, Geom gc, const MGCoef& c,
-            const Couple& cp, hipStream_t st) {
+void down_t(const void* t, const double* tscale, void* x, void* tc, void* tout, const void* kap, Geom g, Geom gc,
+            const MGCoef& c, const Couple& cp, hipStream_t st) {
   if (cp.nz > 0)
-    down_launch<TV, TS, TC, true>((const TV*)t, tscale, (TS*)x, (TS*)tc, (const TC*)kap, g, gc, c, cp, st);
+    down_launch<TV, TS, TC, true>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c, cp, st);
   else
-    down_launch<TV, TS, TC, false>((const TV*)t, tscale, (TS*)x, (TS*)tc, (const TC*)kap, g, gc, c, cp, st);
+    down_launch<TV, TS, TC, false>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c, cp, st);
 }
 
-template <typename TV, typename TS, typename TC, bool CP, int TX, int TY>
-void up_tiles(const TV* tt, const double* tscale, const TS* xx, const TS* ee, TV* oo, const TC* kk, Geom g, Geom gc,
-              const MGCoef& c, const Couple& cp, hipStream_t st) {
+template <typename TT, typename TS, typename TO, typename TC, int TX, int TY>
+void up_tiles(const TT* tt, const TS* xx, const TS* ee, TO* oo, const TC* kk, Geom g, Geom gc, const MGCoef& c,
+              hipStream_t st) {
   const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
   switch (c.deg) {
-    case 1: mg_up_kernel<TV, TS, TC, 1, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
-    case 2: mg_up_kernel<TV, TS, TC, 2, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
-    default: mg_up_kernel<TV, TS, TC, 3, TX, TY, CP><<<grid, NT, 0, st>>>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp); break;
+    case 1: mg_up_kernel<TT, TS, TO, TC, 1, TX, TY><<<grid, NT, 0, st>>>(tt, xx, ee, oo, kk, g, gc, c); break;
+    case 2: mg_up_kernel<TT, TS, TO, TC, 2, TX, TY><<<grid, NT, 0, st>>>(tt, xx, ee, oo, kk, g, gc, c); break;
+    default: mg_up_kernel<TT, TS, TO, TC, 3, TX, TY><<<grid, NT, 0, st>>>(tt, xx, ee, oo, kk, g, gc, c); break;
   }
 }
 
-template <typename TV, typename TS, typename TC, bool CP>
-void up_launch(const TV* tt, const double* tscale, const TS* xx, const TS* ee, TV* oo, const TC* kk, Geom g, Geom gc,
-               const MGCoef& c, const Couple& cp, hipStream_t st) {
+template <typename TT, typename TS, typename TO, typename TC>
+void up_t(const void* t, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc, const MGCoef& c,
+          hipStream_t st) {
   if (g.N < kSmallLevel)
-    up_tiles<TV, TS, TC, CP, TXS, TYS>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp, st);
+    up_tiles<TT, TS, TO, TC, TXS, TYS>((const TT*)t, (const TS*)x, (const TS*)e, (TO*)out, (const TC*)kap, g, gc, c,
+                                       st);
   else
-    up_tiles<TV, TS, TC, CP, TXD, TYD>(tt, tscale, xx, ee, oo, kk, g, gc, c, cp, st);
-}
-
-template <typename TV, typename TS, typename TC>
-void up_t(const void* t, const double* tscale, const void* x, const void* e, void* out, const void* kap, Geom g, Geom gc,
-          const MGCoef& c, const Couple& cp, hipStream_t st) {
-  if (cp.nz > 0)
-    up_launch<TV, TS, TC, true>((const TV*)t, tscale, (const TS*)x, (const TS*)e, (TV*)out, (const TC*)kap, g, gc, c, cp,
-                                st);
-  else
-    up_launch<TV, TS, TC, false>((const TV*)t, tscale, (const TS*)x, (const TS*)e, (TV*)out, (const TC*)kap, g, gc, c,
-                                 cp, st);
+    up_tiles<TT, TS, TO, TC, TXD, TYD>((const TT*)t, (const TS*)x, (const TS*)e, (TO*)out, (const TC*)kap, g, gc, c,
+                                       st);
 }
 
 }  // namespace
 
-void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, const void* kappa,
-                    Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st) {
+void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, void* tout,
+                    const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st) {
   if (prec == 0) {
-    down_t<double, double, double>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
+    down_t<double, double, double>(t, tscale, x, tc, tout, kappa, g, gc, c, cp, st);
   } else if (prec == 1) {
     if (t_is_f64)
-      down_t<double, float, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
+      down_t<double, float, float>(t, tscale, x, tc, tout, kappa, g, gc, c, cp, st);
     else
-      down_t<float, float, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
+      down_t<float, float, float>(t, tscale, x, tc, tout, kappa, g, gc, c, cp, st);
   } else {
     if (t_is_f64)
-      down_t<double, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
+      down_t<double, bf16, float>(t, tscale, x, tc, tout, kappa, g, gc, c, cp, st);
     else
-      down_t<bf16, bf16, float>(t, tscale, x, tc, kappa, g, gc, c, cp, st);
+      down_t<bf16, bf16, float>(t, tscale, x, tc, tout, kappa, g, gc, c, cp, st);
   }
 }
 
-void launch_mg_up(int prec, bool io_is_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
-                  const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st) {
+void launch_mg_up(int prec, bool finest, const void* t, const void* x, const void* e, void* out, const void* kappa,
+                  Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
   if (prec == 0) {
-    up_t<double, double, double>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
+    up_t<double, double, double, double>(t, x, e, out, kappa, g, gc, c, st);
   } else if (prec == 1) {
-    if (io_is_f64)
-      up_t<double, float, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
+    if (finest)
+      up_t<float, float, double, float>(t, x, e, out, kappa, g, gc, c, st);
     else
-      up_t<float, float, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
+      up_t<float, float, float, float>(t, x, e, out, kappa, g, gc, c, st);
   } else {
-    if (io_is_f64)
-      up_t<double, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
+    if (finest)
+      up_t<float, bf16, double, float>(t, x, e, out, kappa, g, gc, c, st);
     else
-      up_t<bf16, bf16, float>(t, tscale, x, e, out, kappa, g, gc, c, cp, st);
+      up_t<bf16, bf16, bf16, float>(t, x, e, out, kappa, g, gc, c, st);
   }
 }
 

@@ -79,6 +79,7 @@ struct Level {
   void* t = nullptr;        // right-hand side (levels >= 1)
   void* x = nullptr;        // pre-smoothed iterate (levels < L-1)
   void* e = nullptr;        // level result / coarse correction (levels >= 1)
+  void* tp = nullptr;       // finest level: the smoother's right-hand side in the compute type (DOWN -> UP)
   bool own64 = false;
 };
 
@@ -439,6 +440,11 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
       CHK(dev_alloc(&lev.x, pb));
       HIPCHK(hipMemsetAsync(lev.x, 0, pb, s));
     }
+    if (l == 0 && L > 1) {
+      const size_t tb = lev.g.plane * (st->prec == 0 ? sizeof(double) : sizeof(float));
+      CHK(dev_alloc(&lev.tp, tb));
+      HIPCHK(hipMemsetAsync(lev.tp, 0, tb, s));
+    }
   }
   CHK(check_launch());
   // Chebyshev coefficients per (stage, level) from power-iteration estimates
@@ -758,15 +764,15 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
     return check_launch();
   }
   std::vector<Level>& lv = st->lv;
-  launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
+  // the finest DOWN stores the right-hand side it smoothed (scaled, with the stage coupling) for the finest UP
+  launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].tp, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
   for (int l = 1; l < L - 1; ++l)
-    launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], none,
-                   s);
+    launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, nullptr, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l],
+                   none, s);
   launch_mg_coarse(pr, false, lv[L - 1].t, nullptr, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
   for (int l = L - 2; l >= 1; --l)
-    launch_mg_up(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l],
-                 none, s);
-  launch_mg_up(pr, true, t, tscale, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
+    launch_mg_up(pr, false, lv[l].t, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+  launch_mg_up(pr, true, lv[0].tp, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
   return check_launch();
 }
 
@@ -1447,6 +1453,7 @@ void irk_stepper_destroy(irk_stepper* st) {
     dev_free(L.t);
     dev_free(L.x);
     dev_free(L.e);
+    dev_free(L.tp);
   }
   for (void* p : st->binv) dev_free(p);
   for (size_t l = 0; l < st->ml.size(); ++l) {
