@@ -231,6 +231,7 @@ def main():
                                + (", DIRK stage-by-stage solves" if args.stage_type == "dirk" else ""),
                    "N": N, "dofs": n, "stages": s},
         "fgmres_its_per_step": stats["fgmres_its_total"] / max(1, args.steps),
+        "discarded_steps_per_step": stats["arnoldi_discarded"] / max(1, args.steps),
         "setup_s": setup_s,
         "solver": {"tableau": args.tableau, "stage_type": args.stage_type, "precond": args.precond,
                    "splitting": args.splitting, "orth": args.orth, "guess": args.guess,

@@ -117,6 +117,7 @@ typedef struct {
   int forward_advances;  /* adjoint only: forward steps recomputed by revolve  */
   double last_rel_resid; /* |f - Acal k| / |f| of the last solve               */
   int failed_step;       /* index of the step that failed, -1 if none          */
+  int arnoldi_discarded; /* Arnoldi steps launched ahead of the convergence test and not used */
 } irk_stats;
 
 typedef struct irk_problem irk_problem;

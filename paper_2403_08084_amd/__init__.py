@@ -92,6 +92,7 @@ class Stats(ctypes.Structure):
         ("forward_advances", ctypes.c_int),
         ("last_rel_resid", ctypes.c_double),
         ("failed_step", ctypes.c_int),
+        ("arnoldi_discarded", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -212,6 +212,9 @@ struct D2Args {
   double* w;
   long len;
   double* res;
+  // optional: the same coefficients written a second time into pinned host memory (the device address of
+  // a hipHostMalloc'ed, coherent buffer), so that the host reads them once the step's event has completed
+  double* mirror = nullptr;
 };
 void launch_dcgs2_dots(const D2Args& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);

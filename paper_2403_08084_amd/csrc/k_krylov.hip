@@ -236,6 +236,7 @@ __global__ __launch_bounds__(NF2) void dcgs2_finish_kernel(D2Args a, ReduceWork 
     for (int w = 0; w < W2; ++w) sm += red[k * W2 + w];
     tot[k] = sm;
     a.res[k] = sm;
+    if (a.mirror) a.mirror[k] = sm;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -250,12 +251,15 @@ __global__ __launch_bounds__(NF2) void dcgs2_finish_kernel(D2Args a, ReduceWork 
     const double beta = ok ? sqrt(b2) : 0.0;
     const double ib = ok ? 1.0 / beta : 0.0;
     const double h = (tot[2 * NV + 1] - as) * ib;
-    a.res[CNT] = beta;
-    a.res[CNT + 1] = ib;
-    a.res[CNT + 2] = h;
-    a.res[CNT + 3] = tot[2 * NV + 2] - ns - h * h;
-    a.res[CNT + 4] = ok ? 0.0 : 1.0;
+    const double tail[5] = {beta, ib, h, tot[2 * NV + 2] - ns - h * h, ok ? 0.0 : 1.0};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a.res[CNT + k] = tail[k];
+    if (a.mirror)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) a.mirror[CNT + k] = tail[k];
   }
+  // the host reads the mirror after the step's completion signal: make the stores visible system-wide
+  if (a.mirror) __threadfence_system();
 }
 
 template <int NV, int U>

@@ -131,6 +131,12 @@ struct irk_stepper {
   ReduceWork rw{};
   bool have_prev = false;
   hipStream_t cap = nullptr;              // library-owned stream used only to capture graphs
+  // Arnoldi steps may run one ahead of the host: step j leaves its reduction in slot j % 2 of dres and
+  // of the pinned, device-visible mirror hmir, and the host waits for step j's event alone
+  double* hmir = nullptr;      // host address of the mirror (2 slots of kDcgs2Res)
+  double* hmir_dev = nullptr;  // its device address
+  hipEvent_t step_ev[2] = {nullptr, nullptr};  // recorded on the solver's stream after step j
+  hipEvent_t norm_ev = nullptr;                // behind the initial norms of a solve
   // measurement hook: events around every launch of one kernel family (eager launches only)
   int timer_family = -1;
   std::vector<hipEvent_t> timer_ev;       // pairs (start, end)
@@ -146,12 +152,14 @@ struct irk_stepper {
 
 namespace {
 
+// a step is launched ahead only while the predicted residual estimate exceeds this multiple of the target
+constexpr double kLookaheadMargin = 4.0;
 constexpr int RSTRIDE = kMaxRestart + 2;
 double* res_slot(irk_stepper* st, int which) { return st->dres + (long)which * RSTRIDE; }
 double* sigma_dev(irk_stepper* st) { return st->dres + 4L * RSTRIDE; }
 double* ycoef_dev(irk_stepper* st) { return st->dres + 5L * RSTRIDE; }
-double* dcgs2_dev(irk_stepper* st) { return st->dres + 6L * RSTRIDE; }
-constexpr long DRES_LEN = 6L * RSTRIDE + kDcgs2Res;
+double* dcgs2_dev(irk_stepper* st, int slot) { return st->dres + 6L * RSTRIDE + (long)slot * kDcgs2Res; }
+constexpr long DRES_LEN = 6L * RSTRIDE + 2L * kDcgs2Res;
 
 // length of the Krylov vectors of the current system
 long sys_len(const irk_stepper* st) { return st->sys < 0 ? st->vlen : st->g.plane; }
@@ -857,7 +865,7 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
     // then one reduction and one update pass: V_j <- q_j, V_{j+1} <- the next direction
     CHK(precondition(st, Vj, nullptr, Zj, trans, s));
     CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
-    D2Args d{st->V, n, j, Vj, Vn, n, dcgs2_dev(st)};
+    D2Args d{st->V, n, j, Vj, Vn, n, dcgs2_dev(st, j & 1), st->hmir_dev + (long)(j & 1) * kDcgs2Res};
     hipEvent_t e0, e1, e2, e3;
     CHK(timer_pair(st, 0, &e0, &e1));
     if (e0) st->timer_bytes += dcgs2_bytes(st, j, n, false);
@@ -931,6 +939,7 @@ struct SolveInfo {
   int its = 0, restarts = 0;
   double rel = 0;
   int solves = 0, its_max = 0;
+  int discarded = 0;  // Arnoldi steps launched ahead of the host's decision and not used
 };
 
 // Least-squares estimate of FGMRES with the (ncol+1) x ncol Hessenberg H (row stride m): Givens QR from
@@ -971,28 +980,40 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
   const long n = sys_len(st);
   double* h = st->hres;
   info = SolveInfo{};
-  CHK(norm2(st, f, n, res_slot(st, 0), nullptr, s));
-  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const double fnorm = std::sqrt(h[0]);
-  if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
-  if (fnorm == 0.0) {
-    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  // Enqueue step k and an event behind it: the host can wait for step k alone (its reduction lands in
+  // mirror slot k % 2) while later work is already queued behind it.
+  auto launch_step = [&](int k) -> int {
+    CHK(run_arnoldi(st, k, trans, s));
+    HIPCHK(hipEventRecord(st->step_ev[k & 1], s));
     return IRK_OK;
-  }
+  };
+  // |f| and the initial residual r_0 = V_0 (= f without a guess). Step 0 needs neither norm on the host
+  // (it normalises u_0 from its own reduction), so it is queued before the host waits for them.
+  CHK(norm2(st, f, n, res_slot(st, 0), nullptr, s));
   if (use_guess) {
     CHK(apply_op(st, x, st->V, f, trans, s));
+    CHK(norm2(st, st->V, n, res_slot(st, 0) + 1, nullptr, s));
   } else {
     HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(st->V, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  CHK(norm2(st, st->V, n, res_slot(st, 0), nullptr, s));
-  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  double beta = std::sqrt(h[0]);
+  HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(st->norm_ev, s));
+  CHK(launch_step(0));
+  bool step0_queued = true;
+  HIPCHK(hipEventSynchronize(st->norm_ev));
+  const double fnorm = std::sqrt(h[0]);
+  if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
+  if (fnorm == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    info.discarded = 1;
+    return IRK_OK;
+  }
+  double beta = use_guess ? std::sqrt(h[1]) : fnorm;
   const double target = st->opt.rtol * fnorm;
   if (beta <= target) {
     info.rel = beta / fnorm;
+    info.discarded = 1;
     return IRK_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m), y(m);
@@ -1000,18 +1021,23 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
     std::fill(H.begin(), H.end(), 0.0);
     double g0 = beta;
     int jdone = 0;
+    double est_prev = beta;
+    if (!step0_queued) CHK(launch_step(0));
+    step0_queued = false;
+    int launched = 0;  // highest step enqueued in this cycle
+    int read = 0;      // highest step whose reduction the host has taken
     for (int j = 0; j < m; ++j) {
-      CHK(run_arnoldi(st, j, trans, s));
+      HIPCHK(hipEventSynchronize(st->step_ev[j & 1]));
+      read = j;
+      const double* hj_res = st->hmir + (long)(j & 1) * kDcgs2Res;
       const int cnt = 2 * j + 3;
-      HIPCHK(hipMemcpyAsync(h, dcgs2_dev(st), (cnt + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
       bool finite = true;
-      for (int i = 0; i < cnt + 5; ++i) finite = finite && std::isfinite(h[i]);
+      for (int i = 0; i < cnt + 5; ++i) finite = finite && std::isfinite(hj_res[i]);
       if (!finite) return fail(IRK_EBREAKDOWN, "non-finite Hessenberg entry in FGMRES");
-      const double* a = h;
-      const double* sw = h + j;
-      const double bj = h[cnt], hj = h[cnt + 2], nu = h[cnt + 3];
-      if (h[cnt + 4] != 0.0) {
+      const double* a = hj_res;
+      const double* sw = hj_res + j;
+      const double bj = hj_res[cnt], hj = hj_res[cnt + 2], nu = hj_res[cnt + 3];
+      if (hj_res[cnt + 4] != 0.0) {
         // the direction u_j vanished: the Krylov space is invariant and column j-1 is exact
         if (j == 0) return fail(IRK_EBREAKDOWN, "zero initial direction in FGMRES");
         for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += a[i];
@@ -1020,6 +1046,7 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
       }
       if (j == 0) {
         g0 = bj;
+        est_prev = bj;
       } else {
         for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += a[i];
         H[(size_t)j * m + (j - 1)] = bj;
@@ -1032,7 +1059,22 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
       const double est = hessenberg_ls(H, m, jdone, g0, nullptr);
       if (est <= target || H[(size_t)(j + 1) * m + j] <= 1e-300 * std::fabs(hj)) break;
       if (info.its >= st->opt.max_it) break;
+      if (j + 1 < m && launched == j) {
+        CHK(launch_step(j + 1));
+        launched = j + 1;
+      }
+      // Step j+2 goes in behind step j+1 when the last reduction factor, applied once more, still leaves
+      // the estimate well above the target: the host then decides on step j+1 while step j+2 runs.
+      // A step launched this way and not needed is discarded (it writes only V_{j+2}, V_{j+3}, Z_{j+2}).
+      const double rate = est_prev > 0 ? est / est_prev : 1.0;
+      est_prev = est;
+      if (launched == j + 1 && j + 2 < m && info.its + 2 <= st->opt.max_it &&
+          est * std::min(rate, 1.0) > kLookaheadMargin * target) {
+        CHK(launch_step(j + 2));
+        launched = j + 2;
+      }
     }
+    info.discarded += launched - read;
     if (jdone > 0) {
       hessenberg_ls(H, m, jdone, g0, y.data());
       std::copy(y.begin(), y.begin() + jdone, h);
@@ -1198,6 +1240,7 @@ void add_stats(irk_stats* stats, const SolveInfo& si) {
   stats->fgmres_its_total += si.its;
   stats->fgmres_its_max = std::max(stats->fgmres_its_max, std::max(si.its_max, si.solves ? 0 : si.its));
   stats->restarts_total += si.restarts;
+  stats->arnoldi_discarded += si.discarded;
   stats->solves += std::max(1, si.solves);
   stats->last_rel_resid = si.rel;
 }
@@ -1229,6 +1272,7 @@ int stage_solve(irk_stepper* st, const double* f, bool trans, bool use_guess, So
     st->sys = -1;
     info.its += si.its;
     info.restarts += si.restarts;
+    info.discarded += si.discarded;
     info.its_max = std::max(info.its_max, si.its);
     info.rel = std::max(info.rel, si.rel);
     info.solves++;
@@ -1484,6 +1528,13 @@ void irk_stepper_destroy(irk_stepper* st) {
       if (g) (void)hipGraphExecDestroy(g);
   for (hipEvent_t e : st->timer_ev) (void)hipEventDestroy(e);
   if (st->cap) (void)hipStreamDestroy(st->cap);
+  for (int i = 0; i < 2; ++i)
+    if (st->step_ev[i]) (void)hipEventDestroy(st->step_ev[i]);
+  if (st->norm_ev) (void)hipEventDestroy(st->norm_ev);
+  if (st->hmir) {
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(st->hmir);
+  }
   if (st->hres) (void)hipHostFree(st->hres);
   delete st;
 }
@@ -1646,6 +1697,15 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
     rc = fail(IRK_ENOMEM, "hipHostMalloc failed");
   if (rc == IRK_OK && hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess)
     rc = fail(IRK_EHIP, "stream creation failed");
+  if (rc == IRK_OK && (hipHostMalloc((void**)&st->hmir, 2 * kDcgs2Res * sizeof(double), hipHostMallocCoherent) !=
+                            hipSuccess ||
+                        hipHostGetDevicePointer((void**)&st->hmir_dev, st->hmir, 0) != hipSuccess))
+    rc = fail(IRK_ENOMEM, "pinned coefficient mirror allocation failed");
+  for (int i = 0; i < 2 && rc == IRK_OK; ++i)
+    if (hipEventCreateWithFlags(&st->step_ev[i], hipEventDisableTiming) != hipSuccess)
+      rc = fail(IRK_EHIP, "event creation failed");
+  if (rc == IRK_OK && hipEventCreateWithFlags(&st->norm_ev, hipEventDisableTiming) != hipSuccess)
+    rc = fail(IRK_EHIP, "event creation failed");
   if (rc == IRK_OK) rc = setup_multigrid(st, hs);
   if (rc == IRK_OK && o.precond == IRK_PC_MONOLITHIC) rc = setup_mmg(st, hs);
   if (rc == IRK_OK && hipStreamSynchronize(hs) != hipSuccess) rc = fail(IRK_EHIP, "setup synchronisation failed");
