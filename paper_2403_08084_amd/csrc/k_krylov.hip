@@ -186,8 +186,12 @@ __device__ __forceinline__ void process2(const D2Args& a, long q0, long stride, 
   }
 }
 
+// The grid holds 4 waves per SIMD (dcgs2_blocks), so the kernel may take up to 128 VGPRs: the 2NV+3 FP64
+// accumulators then leave room for all NV+2 loads of an element to be in flight at once (capped at 64 VGPRs
+// for 8 waves, the pass fell from 5.3 to 3.7 TB/s at NV = 10..14).
 template <int NV>
-__global__ __launch_bounds__(NT) void dots2_kernel(D2Args a, ReduceWork rw) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 4))) void dots2_kernel(D2Args a,
+                                                                                             ReduceWork rw) {
   constexpr int CNT = 2 * NV + 3;
   constexpr int U = NV <= 2 ? 4 : (NV <= 8 ? 2 : 1);
   double acc[CNT];
