@@ -164,7 +164,7 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
     for (int idx = threadIdx.x; idx < RX * RY; idx += NT) {
       const int lj = idx / RX, li = idx - lj * RX;
       TC v = (TC)0;
-      if (interior(ox + li, oy + lj, N)) v = c0 * sT[idx] / diag_at<TC, KX>(sK, li, lj, m, alpha);
+      if (interior(ox + li, oy + lj, N)) v = c0 * sT[idx] * recip(diag_at<TC, KX>(sK, li, lj, m, alpha));
       sB[idx] = v;
       sA[idx] = (TC)0;
     }
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(NT) void mg_down_kernel(const TV* __restrict__ t, c
       TC Bx, D;
       bx_d<TC, RX, KX>(cur, sK, li, lj, m, alpha, Bx, D);
       const int p = lj * RX + li;
-      prv[p] = cur[p] + beta * (cur[p] - prv[p]) + gam * (sT[p] - Bx) / D;
+      prv[p] = cur[p] + beta * (cur[p] - prv[p]) + gam * (sT[p] - Bx) * recip(D);
     }
     __syncthreads();
     TC* tmp = cur;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TT* __restrict__ t, con
       if (interior(ox + li, oy + lj, N)) {
         TC Bx, D;
         bx_d<TC, RX, KX>(sA, sK, li, lj, m, alpha, Bx, D);
-        v = sA[p] + c0 * (sT[p] - Bx) / D;
+        v = sA[p] + c0 * (sT[p] - Bx) * recip(D);
       }
       sB[p] = v;
     }
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(NT) void mg_up_kernel(const TT* __restrict__ t, con
       TC Bx, D;
       bx_d<TC, RX, KX>(cur, sK, li, lj, m, alpha, Bx, D);
       const int p = lj * RX + li;
-      prv[p] = cur[p] + beta * (cur[p] - prv[p]) + gam * (sT[p] - Bx) / D;
+      prv[p] = cur[p] + beta * (cur[p] - prv[p]) + gam * (sT[p] - Bx) * recip(D);
     }
     __syncthreads();
     TC* tmp = cur;

@@ -133,12 +133,13 @@ __device__ __forceinline__ void block_solve(TC C[S][S], TC r[S]) {
 // per level on the host); kd = K_vv of the node
 template <typename TC, int S>
 __device__ __forceinline__ void patch_apply(const MMGCoef& c, TC kd, TC r[S]) {
-  const TC tau = c.ia ? (TC)c.tfac / kd : (TC)c.tfac * kd;
-  const TC w = c.ia ? (TC)c.wfac / kd : (TC)c.wfac;
+  const TC ikd = c.ia ? recip(kd) : (TC)1;
+  const TC tau = c.ia ? (TC)c.tfac * ikd : (TC)c.tfac * kd;
+  const TC w = (TC)c.wfac * ikd;
   TC d = (TC)c.det[S];
 #pragma unroll
   for (int k = S - 1; k >= 0; --k) d = d * tau + (TC)c.det[k];
-  const TC f = w / d;
+  const TC f = w * recip(d);
   TC z[S];
 #pragma unroll
   for (int q = 0; q < S; ++q) {

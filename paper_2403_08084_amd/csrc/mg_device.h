@@ -16,6 +16,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(b >> 16);
 }
 
+// 1/x for the smoothers' diagonal scalings: v_rcp_f32 (within 1 ulp) in the FP32 compute type, where the
+// correctly rounded division costs about ten instructions; exact division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename TC>
 __device__ __forceinline__ TC ld(const double* p) { return (TC)*p; }
 template <typename TC>
