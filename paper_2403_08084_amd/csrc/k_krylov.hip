@@ -160,7 +160,7 @@ __global__ __launch_bounds__(NF) void finish_kernel(OrthoArgs a, ReduceWork rw, 
 // one reduction giving Q^T u, Q^T w, u.u, u.w, w.w; u is then re-orthogonalised and normalised into
 // q_j and w projected against Q and q_j in one streaming update pass.
 
-constexpr int NF2 = 256;  // threads of the DCGS2 finishing kernel (each sums nb / NF2 partials)
+constexpr int NF2 = 1024;  // threads of the DCGS2 finishing kernel (one wave per reduced value)
 
 template <int NV, int U>
 __device__ __forceinline__ void process2(const D2Args& a, long q0, long stride, double (&acc)[2 * NV + 3]) {
@@ -219,28 +219,29 @@ __global__ __launch_bounds__(NF2) void dcgs2_finish_kernel(D2Args a, ReduceWork 
   constexpr int CNT = 2 * NV + 3;
   constexpr int W2 = NF2 / 64;
   const int mb = rw.max_blocks;
-  double fin[CNT];
-#pragma unroll
-  for (int k = 0; k < CNT; ++k) fin[k] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += NF2)
-#pragma unroll
-    for (int k = 0; k < CNT; ++k) fin[k] += rw.partial[(long)k * mb + b];
-  __shared__ double red[CNT * W2];
   __shared__ double tot[CNT];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < CNT; ++k) {
-    const double sm = wave_sum(fin[k]);
-    if (lane == 0) red[k * W2 + wid] = sm;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < CNT; k += NF2) {
+  // wave w sums the partials of values w, w + W2, ...: every lane adds its partials (independent loads, all
+  // in flight at once), then the wave reduces across lanes
+  for (int k = wid; k < CNT; k += W2) {
+    const double* p = rw.partial + (long)k * mb;
     double sm = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+      double v[16];
 #pragma unroll
-    for (int w = 0; w < W2; ++w) sm += red[k * W2 + w];
-    tot[k] = sm;
-    a.res[k] = sm;
-    if (a.mirror) a.mirror[k] = sm;
+      for (int i = 0; i < 16; ++i) {
+        const int b = b0 + lane + 64 * i;
+        v[i] = b < nb ? p[b] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sm += v[i];
+    }
+    sm = wave_sum(sm);
+    if (lane == 0) {
+      tot[k] = sm;
+      a.res[k] = sm;
+      if (a.mirror) a.mirror[k] = sm;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
