@@ -76,6 +76,13 @@ enum { IRK_SPLIT_AI = 0, IRK_SPLIT_IA = 1 };
  * triangular A, AI form) solves the stages one after the other, each by FGMRES on
  * M + dt a_ii K preconditioned by one V-cycle, with the known stages moved to the right. */
 enum { IRK_STAGE_COUPLED = 0, IRK_STAGE_DIRK = 1 };
+/* Arnoldi steps queued ahead of the host's convergence test (IRK_ORTH_DCGS2 only). OFF queues each
+ * step after the host has read the previous one. ADAPTIVE (default) queues step 0 before the host reads
+ * the initial norms, and step j+2 behind step j+1 while the last residual reduction factor, applied once
+ * more, leaves the estimate above 4x the target. ALWAYS queues step j+2 whenever the cycle has one. A step
+ * queued ahead and not used writes only Krylov vectors the solution does not depend on, so all three give
+ * bit-identical results; irk_stats.arnoldi_discarded counts such steps. */
+enum { IRK_LOOKAHEAD_OFF = 0, IRK_LOOKAHEAD_ADAPTIVE = 1, IRK_LOOKAHEAD_ALWAYS = 2 };
 
 /* Butcher tableau (Section 2): A is s x s row-major, b and c have s entries.
  * Host memory; copied at stepper creation. */
@@ -105,6 +112,7 @@ typedef struct {
                          0: launch every kernel eagerly (same arithmetic)          */
   int splitting;      /* IRK_SPLIT_AI (default) or IRK_SPLIT_IA                    */
   int stage_type;     /* IRK_STAGE_COUPLED (default) or IRK_STAGE_DIRK             */
+  int lookahead;      /* IRK_LOOKAHEAD_ADAPTIVE (default), IRK_LOOKAHEAD_OFF or IRK_LOOKAHEAD_ALWAYS */
 } irk_options;
 
 /* Per-call statistics (host struct, filled if non-NULL). */

@@ -17,6 +17,8 @@ Stepper options (fields of irk_options; defaults from irk_options_default):
   stage_type    STAGE_COUPLED or STAGE_DIRK (stage-by-stage solves, lower-triangular A)
   mg_precision  F64, F32 or BF16 storage of the multigrid vectors (FGMRES stays FP64)
   orth          ORTH_DCGS2 (one reduction per Arnoldi step), ORTH_CGS2, ORTH_CGS_SELECTIVE
+  lookahead     LOOKAHEAD_ADAPTIVE (queue the next Arnoldi step before the host's convergence test
+                while the residual history predicts it is needed), LOOKAHEAD_OFF, LOOKAHEAD_ALWAYS
   rtol, restart, max_it, mg_coarse_n, cheb_degree, cheb_lo, cheb_hi, power_its, initial_guess, use_graphs
 
 Example (1024^2, Radau IIA(3), mixed precision, monolithic multigrid):
@@ -42,6 +44,7 @@ STAGE_COUPLED, STAGE_DIRK = 0, 1
 F64, F32, BF16 = 0, 1, 2
 ORTH_CGS2, ORTH_CGS_SELECTIVE, ORTH_DCGS2 = 0, 1, 2
 GUESS_ZERO, GUESS_PREV = 0, 1
+LOOKAHEAD_OFF, LOOKAHEAD_ADAPTIVE, LOOKAHEAD_ALWAYS = 0, 1, 2
 
 _STATUS = {IRK_EINVAL: "EINVAL", IRK_ENOMEM: "ENOMEM", IRK_EHIP: "EHIP", IRK_ENOCONV: "ENOCONV",
            IRK_EBREAKDOWN: "EBREAKDOWN"}
@@ -70,6 +73,7 @@ class Options(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("splitting", ctypes.c_int),
         ("stage_type", ctypes.c_int),
+        ("lookahead", ctypes.c_int),
     ]
 
 

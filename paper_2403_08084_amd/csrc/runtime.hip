@@ -999,21 +999,22 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
   }
   HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(st->norm_ev, s));
-  CHK(launch_step(0));
-  bool step0_queued = true;
+  const int look = st->opt.lookahead;
+  bool step0_queued = look != IRK_LOOKAHEAD_OFF;
+  if (step0_queued) CHK(launch_step(0));
   HIPCHK(hipEventSynchronize(st->norm_ev));
   const double fnorm = std::sqrt(h[0]);
   if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
   if (fnorm == 0.0) {
     HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    info.discarded = 1;
+    info.discarded = step0_queued ? 1 : 0;
     return IRK_OK;
   }
   double beta = use_guess ? std::sqrt(h[1]) : fnorm;
   const double target = st->opt.rtol * fnorm;
   if (beta <= target) {
     info.rel = beta / fnorm;
-    info.discarded = 1;
+    info.discarded = step0_queued ? 1 : 0;
     return IRK_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m), y(m);
@@ -1068,8 +1069,9 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
       // A step launched this way and not needed is discarded (it writes only V_{j+2}, V_{j+3}, Z_{j+2}).
       const double rate = est_prev > 0 ? est / est_prev : 1.0;
       est_prev = est;
-      if (launched == j + 1 && j + 2 < m && info.its + 2 <= st->opt.max_it &&
-          est * std::min(rate, 1.0) > kLookaheadMargin * target) {
+      const bool ahead = look == IRK_LOOKAHEAD_ALWAYS ||
+                         (look == IRK_LOOKAHEAD_ADAPTIVE && est * std::min(rate, 1.0) > kLookaheadMargin * target);
+      if (launched == j + 1 && j + 2 < m && info.its + 2 <= st->opt.max_it && ahead) {
         CHK(launch_step(j + 2));
         launched = j + 2;
       }
@@ -1402,6 +1404,7 @@ void irk_options_default(irk_options* o) {
   o->use_graphs = 1;
   o->splitting = IRK_SPLIT_AI;
   o->stage_type = IRK_STAGE_COUPLED;
+  o->lookahead = IRK_LOOKAHEAD_ADAPTIVE;
 }
 
 int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stream) {
@@ -1567,6 +1570,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   if (o.mg_coarse_n < 1) return fail(IRK_EINVAL, "mg_coarse_n must be >= 1");
   if (o.splitting != IRK_SPLIT_AI && o.splitting != IRK_SPLIT_IA) return fail(IRK_EINVAL, "unknown splitting");
   if (o.stage_type != IRK_STAGE_COUPLED && o.stage_type != IRK_STAGE_DIRK) return fail(IRK_EINVAL, "unknown stage_type");
+  if (o.lookahead < IRK_LOOKAHEAD_OFF || o.lookahead > IRK_LOOKAHEAD_ALWAYS) return fail(IRK_EINVAL, "unknown lookahead");
   if (o.stage_type == IRK_STAGE_DIRK) {
     if (o.splitting != IRK_SPLIT_AI) return fail(IRK_EINVAL, "the DIRK stage type solves the AI form");
     for (int i = 0; i < tab->s; ++i)

@@ -32,6 +32,7 @@ def test_options_default():
     o = P.default_options()
     assert o.precond == P.PC_GS_LOWER and o.restart == 30 and o.rtol == 1e-10
     assert o.orth == P.ORTH_DCGS2 and o.splitting == P.SPLIT_AI and o.stage_type == P.STAGE_COUPLED
+    assert o.lookahead == P.LOOKAHEAD_ADAPTIVE
     assert o.cheb_degree == 2 and o.cheb_lo == 0.25 and o.cheb_hi == 1.1
     assert o.mg_precision == P.F64 and o.use_graphs == 1
     with pytest.raises(TypeError):

@@ -409,3 +409,50 @@ def test_dcgs2_graph_replay_matches_eager_bitwise(prec):
         outs.append((host(u), host(u2)))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[1][0], outs[1][1])
+
+
+@pytest.mark.parametrize("pc,prec", [(P.PC_GS_LOWER, P.F32), (P.PC_MONOLITHIC, P.F32), (P.PC_JACOBI, P.F64)])
+def test_lookahead_modes_agree_bitwise(pc, prec):
+    # a step queued ahead of the convergence test and then not used writes only Krylov vectors beyond the
+    # ones the solution is built from, so every mode gives the same bits; ALWAYS discards one at the end of
+    # each solve (unless it ends at a restart boundary), OFF never
+    N, dt = 96, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    M, K = fem.assemble(N, kap)
+    otab = OT.radau_iia(3)
+    f = synth.random_stage_block(N, 3, 29).ravel()
+    out = {}
+    for look in (P.LOOKAHEAD_OFF, P.LOOKAHEAD_ADAPTIVE, P.LOOKAHEAD_ALWAYS):
+        _, stp = make(N, kap, P.tableaux.radau_iia(3), dt, precond=pc, mg_precision=prec, rtol=1e-10,
+                      lookahead=look)
+        k, stats = stp.solve_stages(dev(f))
+        out[look] = (host(k), stats)
+    k0, s0 = out[P.LOOKAHEAD_OFF]
+    for look in (P.LOOKAHEAD_ADAPTIVE, P.LOOKAHEAD_ALWAYS):
+        assert np.array_equal(out[look][0], k0)
+        assert out[look][1]["fgmres_its_total"] == s0["fgmres_its_total"]
+    assert s0["arnoldi_discarded"] == 0
+    assert out[P.LOOKAHEAD_ALWAYS][1]["arnoldi_discarded"] >= 1
+    ref = step.CoupledLU(M, K, otab["A"], dt).solve(f)
+    assert rel(k0, ref) < 1e-8
+
+
+def test_lookahead_always_matches_off_over_dirk_steps():
+    # several single-stage solves per step, each ending with a discarded step under ALWAYS
+    N, dt, nsteps = 96, 1e-3, 3
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    res = []
+    for look in (P.LOOKAHEAD_OFF, P.LOOKAHEAD_ALWAYS):
+        _, stp = make(N, kap, _DIRK["wso433"][1](), dt, rtol=1e-12, stage_type=P.STAGE_DIRK, lookahead=look)
+        u = dev(u0)
+        _, stats = stp.advance(u, nsteps)
+        res.append((host(u), stats))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1]["arnoldi_discarded"] == 0 and res[1][1]["arnoldi_discarded"] >= nsteps
+
+
+def test_lookahead_rejects_unknown_mode():
+    kap = synth.grf_kappa(16, 1)
+    with pytest.raises(P.IrkError):
+        make(16, kap, P.tableaux.radau_iia(2), 1e-3, lookahead=3)
