@@ -19,7 +19,13 @@ events on its launch stream by the library's measurement hook, algorithmic
 bytes vs the 8 TB/s HBM3E peak), "cpu_baseline" (the CPU oracle on a bounded
 sample of the same workload) and "variants" (the same workload, mixed form,
 solved with the Rana-LD preconditioner in the IA form and with the monolithic
-multigrid cycle).
+multigrid cycle), "copy_ceiling" inside "roofline" (a plain 256 MiB device copy timed
+the same way, the bandwidth a streaming kernel can reach in practice) and "adjoint"
+(the gradient workload: 512 x 512, Radau IIA(3), 40 steps, 8 snapshots, FP64;
+forward and gradient wall times).
+
+Other workloads of the same method: --tableau, --dt, --kappa one, --N, --steps,
+--precision, --precond, --splitting, --stage-type.
 """
 from __future__ import annotations
 
@@ -47,6 +53,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--kappa", choices=["grf", "one"], default="grf",
+                    help="per-element diffusivity: exp(GRF seed 1) or 1 everywhere")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient workload")
     ap.add_argument("--precision", choices=["f32", "bf16", "f64"], default="f32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -106,13 +116,13 @@ def make_tableau(P, name):
             "wso433": T.wsodirk433}[name]()
 
 
-def golden_error(u, steps, tableau="radau3"):
+def golden_error(u, steps, tableau="radau3", workload_matches=True):
     """Relative L2 error of u against the oracle's full-size result (sketch estimate), or None."""
     import numpy as np
 
     import synth
 
-    if not os.path.exists(GOLDEN):
+    if not workload_matches or not os.path.exists(GOLDEN):
         return None
     with open(GOLDEN) as f:
         g = json.load(f)
@@ -176,6 +186,54 @@ def cpu_baseline(N, steps):
             "setup_s": t1 - t0, "solve_s_per_step": (t2 - t1) / max(1, steps)}
 
 
+def copy_ceiling(torch, mib=256, reps=10):
+    """Bandwidth of a plain device-to-device copy (read + write bytes / time), HIP events on the stream."""
+    a = torch.ones(mib * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * mib * 1024 * 1024 * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del a, b
+    return {"achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "unit": "GB/s",
+            "kernel": f"device-to-device copy of {mib} MiB, {reps} times"}
+
+
+def adjoint_timing(P, torch, synth, N=512, steps=40, nsnap=8, dt=1e-3):
+    """Gradient of J = 1/2 |u_N|_M^2 with respect to log kappa (512^2, Radau IIA(3), FP64 multigrid): wall time
+    of the forward steps and of the discrete adjoint with binomial checkpointing (graphs captured beforehand)."""
+    kap = torch.as_tensor(synth.grf_kappa(N, 1)).cuda()
+    u0 = torch.as_tensor(synth.sine_modes_u0(N, 0)[0]).cuda()
+    prob = P.Problem(N, kap)
+    stp = P.Stepper(prob, P.tableaux.radau_iia(3), dt, mg_precision=P.F64)
+    uw = u0.clone()
+    stp.advance(uw, 2)
+    stp.adjoint(u0, 2, 1, uw)
+    u = u0.clone()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    _, fst = stp.advance(u, steps)
+    ev[1].record()
+    lam = prob.apply_mass(u)
+    torch.cuda.synchronize()
+    ev[2].record()
+    _, _, ast = stp.adjoint(u0, steps, nsnap, lam)
+    ev[3].record()
+    torch.cuda.synchronize()
+    fwd, grad = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    return {"workload": f"gradient of 1/2 |u_N|_M^2 w.r.t. log kappa, Q1 {N}x{N}, kappa=exp(GRF seed 1), Radau IIA(3), "
+                        f"dt={dt:g}, {steps} steps, {nsnap} snapshots, P_L, FP64",
+            "forward_ms": fwd, "gradient_ms": grad, "gradient_over_forward": grad / fwd,
+            "forward_its": fst["fgmres_its_total"], "adjoint_its": ast["fgmres_its_total"],
+            "forward_advances": ast["forward_advances"]}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -199,8 +257,9 @@ def main():
     n = (N - 1) ** 2
     tab = make_tableau(P, args.tableau)
     s = len(tab["b"])
-    dt = 1e-3
-    kap = synth.grf_kappa(N, 1)
+    dt = args.dt
+    kap = synth.grf_kappa(N, 1) if args.kappa == "grf" else np.ones(N * N)
+    golden_ok = args.kappa == "grf" and dt == 1e-3  # the stored oracle result is for this workload
     u0, _ = synth.sine_modes_u0(N, 0)
     prob = P.Problem(N, torch.as_tensor(kap).cuda())
     u0d = torch.as_tensor(u0).cuda()
@@ -222,7 +281,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"f32": "f64+f32", "bf16": "f64+bf16", "f64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"diffusion Q1 {N}x{N}, kappa=exp(GRF seed 1), {tab['name']}, dt=1e-3, "
+        "config": {"workload": f"diffusion Q1 {N}x{N}, "
+                               + ("kappa=exp(GRF seed 1)" if args.kappa == "grf" else "kappa=1")
+                               + f", {tab['name']}, dt={dt:g}, "
                                f"FGMRES({args.restart}) rtol 1e-10, " + (
                                    "1 monolithic GMG V-cycle Cheb(2)" if args.precond == "mmg" else
                                    f"P_{ {'gs': 'L', 'jacobi': 'D', 'rana': 'LD', 'gsu': 'U'}[args.precond]} + "
@@ -237,14 +298,14 @@ def main():
                    "splitting": args.splitting, "orth": args.orth, "guess": args.guess,
                    "restart": args.restart,
                    "coarse_n": args.coarse_n},
-        "error_vs_oracle": golden_error(uh, args.steps, args.tableau),
+        "error_vs_oracle": golden_error(uh, args.steps, args.tableau, golden_ok),
     }
     if not args.no_fp64 and prec != P.F64:
         _, u64, ms64, st64, _ = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, P.F64, opts)
         u64h = u64.cpu().numpy()
         out["fp64"] = {"value": n * s * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                        "fgmres_its_per_step": st64["fgmres_its_total"] / max(1, args.steps),
-                       "error_vs_oracle": golden_error(u64h, args.steps, args.tableau)}
+                       "error_vs_oracle": golden_error(u64h, args.steps, args.tableau, golden_ok)}
         out["mixed_over_fp64"] = value / out["fp64"]["value"]
         out["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(uh - u64h) / np.linalg.norm(u64h))
     if not args.no_variants and args.tableau == "radau3" and args.stage_type == "coupled":
@@ -257,7 +318,7 @@ def main():
             _, uv, msv, stv, _ = timed_run(P, torch, prob, tab, dt, u0d, args.steps, args.warmup, prec, o2)
             out["variants"][name] = {"value": n * s * args.steps / (msv / 1e3), "ms_per_step": msv / args.steps,
                                      "fgmres_its_per_step": stv["fgmres_its_total"] / max(1, args.steps),
-                                     "error_vs_oracle": golden_error(uv.cpu().numpy(), args.steps, args.tableau)}
+                                     "error_vs_oracle": golden_error(uv.cpu().numpy(), args.steps, args.tableau, golden_ok)}
             del uv
     if not args.no_roofline:
         # same steps again with the measurement hook on the Gram-Schmidt pass (launched eagerly)
@@ -274,7 +335,10 @@ def main():
                                       if args.orth == "dcgs2" else "ortho_kernel (streaming Gram-Schmidt pass)"),
                            "launches": launches,
                            "avg_us": 1e3 * kms / max(1, launches),
-                           "algorithmic_bytes_per_launch": kbytes / max(1, launches)}
+                           "algorithmic_bytes_per_launch": kbytes / max(1, launches),
+                           "copy_ceiling": copy_ceiling(torch)}
+    if not args.no_adjoint and not args.no_variants:
+        out["adjoint"] = adjoint_timing(P, torch, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, args.cpu_steps)
     print(json.dumps(out))

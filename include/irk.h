@@ -181,8 +181,10 @@ int irk_apply_stage_operator(const irk_stepper *st, const double *x, double *y, 
  * eq:bigdecomp) on the whole system: additive Schwarz over each vertex's s stage values
  * (an s x s solve per node) inside Chebyshev smoothing, stage-wise transfers, a dense
  * solve on the coarsest level (halving while N is even and N > mg_coarse_n or
- * s (N-1)^2 > 1024). With transpose != 0 the preconditioner of the transposed system
- * (built from A^T) is applied. v, z: device s*n. */
+ * s (N-1)^2 > 1024). With transpose != 0 the preconditioner of the transposed system is
+ * applied: for the block preconditioners the transpose of the forward one, I (x) M + dt Atil^T (x) K
+ * (IA: Atil^{-T} (x) M + dt I (x) K), by block substitution in the opposite order; the monolithic
+ * cycle is built on the transposed operator. v, z: device s*n. */
 int irk_apply_preconditioner(const irk_stepper *st, const double *v, double *z, int transpose, void *stream);
 
 /* a4 (Section 3.1 diagonal blocks): z = one V-cycle for (M + dt*atil_ii*K) z = t with zero

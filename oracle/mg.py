@@ -244,19 +244,28 @@ def preconditioner_matrix(kind, A):
     raise ValueError(kind)
 
 
-def apply_block_preconditioner(kind, A, dt, K, v, block_solve):
-    """Apply P^{-1} for the AI-form stage preconditioner P = I (x) M + dt Atil (x) K.
+def _upper(kind, trans):
+    # gs_upper's Atil is upper triangular, the others lower (or diagonal); transposing swaps the two
+    return (kind == "gs_upper") != bool(trans)
+
+
+def apply_block_preconditioner(kind, A, dt, K, v, block_solve, trans=False):
+    """Apply P^{-1} for the AI-form stage preconditioner P = I (x) M + dt Atil (x) K, or with
+    trans=True its transpose P^T = I (x) M + dt Atil^T (x) K (M, K symmetric), the preconditioner of
+    the transposed system I (x) M + dt A^T (x) K.
 
     kind: "jacobi" (P_D), "gs_lower" (P_L), "gs_upper" (P_U) or "rana_ld" (P_LD); v is
     stage-major (s*n,). Atil is triangular, so P is block triangular and is inverted by
     block substitution: forward (i = 0, 1, ...) for a lower Atil, backward for an upper one,
         z_i = B_i^{-1} (v_i - dt K sum_{j already solved} atil_ij z_j).
     block_solve(i, t) must return (an approximation of) B_i^{-1} t with
-    B_i = M + dt*atil_ii*K.
+    B_i = M + dt*atil_ii*K (the diagonal is the same for Atil^T).
     """
     Atil = preconditioner_matrix(kind, A)
+    if trans:
+        Atil = Atil.T
     s = Atil.shape[0]
-    order = range(s - 1, -1, -1) if kind == "gs_upper" else range(s)
+    order = range(s - 1, -1, -1) if _upper(kind, trans) else range(s)
     V = np.asarray(v).reshape(s, -1)
     Z = np.zeros_like(V)
     done = []
@@ -293,9 +302,10 @@ def vcycle_block_solver(hier: Hierarchy, A):
 # ---------------------------------------------------------------- IA form (eq:block_struct_IA)
 
 
-def apply_ia_block_preconditioner(kind, A, dt, M, K, v, block_solve):
+def apply_ia_block_preconditioner(kind, A, dt, M, K, v, block_solve, trans=False):
     """Apply P^{-1} for the IA-form stage preconditioner P = Atil^{-1} (x) M + dt I (x) K
-    (eq:pcbjac, eq:pcbgs, eq:pcranald as printed, for eq:block_struct_IA).
+    (eq:pcbjac, eq:pcbgs, eq:pcranald as printed, for eq:block_struct_IA), or with trans=True its
+    transpose Atil^{-T} (x) M + dt I (x) K.
 
     Atil is triangular, so C = Atil^{-1} is triangular too and P is block triangular with diagonal
     blocks c_ii M + dt K (c_ii = 1/atil_ii); the stages are coupled through M:
@@ -303,9 +313,11 @@ def apply_ia_block_preconditioner(kind, A, dt, M, K, v, block_solve):
     block_solve(i, t) must return (an approximation of) (c_ii M + dt K)^{-1} t.
     """
     Atil = preconditioner_matrix(kind, A)
+    if trans:
+        Atil = Atil.T
     C = np.linalg.inv(Atil)
     s = Atil.shape[0]
-    order = range(s - 1, -1, -1) if kind == "gs_upper" else range(s)
+    order = range(s - 1, -1, -1) if _upper(kind, trans) else range(s)
     V = np.asarray(v).reshape(s, -1)
     Z = np.zeros_like(V)
     done = []

@@ -795,9 +795,10 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
   const int ns = st->s;
   const Coefs a = ptil_of(st, trans);
   const double* Ci = st->Ci[trans ? 1 : 0];
-  // Atil is lower triangular (forward substitution) except for P_U (backward substitution); stage i is
-  // coupled to the nc stages solved before it, which sit contiguously from stage j0 on
-  const bool upper = st->opt.precond == IRK_PC_GS_UPPER;
+  // Atil is lower triangular (forward substitution) except for P_U (backward substitution), and the
+  // transposed system uses Atil^T (the other way round); stage i is coupled to the nc stages solved
+  // before it, which sit contiguously from stage j0 on
+  const bool upper = (st->opt.precond == IRK_PC_GS_UPPER) != trans;
   for (int step = 0; step < ns; ++step) {
     const int i = upper ? ns - 1 - step : step;
     const int j0 = upper ? i + 1 : 0;
@@ -1598,8 +1599,8 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   st->opt = o;
   {
     // Atil: D, L + D, U + D (additive split, eq:pcbjac / eq:pcbgs and its upper variant) or L1 D of
-    // A = L1 D U1 (eq:pcranald); the transposed system A^T uses D, tril(A^T), triu(A^T) or U1^T D
-    // (A^T = U1^T D L1^T has the same D)
+    // A = L1 D U1 (eq:pcranald); the transposed system is preconditioned by the transpose of the forward
+    // preconditioner, I (x) M + dt Atil^T (x) K (IA: Atil^{-T} (x) M + dt I (x) K), with the same diagonal
     double L1[kMaxStages * kMaxStages] = {}, U1[kMaxStages * kMaxStages] = {}, D[kMaxStages] = {};
     if (o.precond == IRK_PC_RANA_LD) {
       double W[kMaxStages * kMaxStages];
@@ -1621,22 +1622,19 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
     }
     for (int i = 0; i < s; ++i)
       for (int j = 0; j < s; ++j) {
-        double f = 0, t = 0;
-        if (o.precond == IRK_PC_JACOBI || o.precond == IRK_PC_MONOLITHIC) {
-          f = t = (i == j) ? tab->A[i * s + i] : 0.0;
-        } else if (o.precond == IRK_PC_GS_LOWER) {
+        double f = 0;
+        if (o.precond == IRK_PC_JACOBI || o.precond == IRK_PC_MONOLITHIC)
+          f = (i == j) ? tab->A[i * s + i] : 0.0;
+        else if (o.precond == IRK_PC_GS_LOWER)
           f = (j <= i) ? tab->A[i * s + j] : 0.0;
-          t = (j <= i) ? tab->A[j * s + i] : 0.0;
-        } else if (o.precond == IRK_PC_GS_UPPER) {
+        else if (o.precond == IRK_PC_GS_UPPER)
           f = (j >= i) ? tab->A[i * s + j] : 0.0;
-          t = (j >= i) ? tab->A[j * s + i] : 0.0;
-        } else {
+        else
           f = (j <= i) ? L1[i * s + j] * D[j] : 0.0;
-          t = (j <= i) ? U1[j * s + i] * D[j] : 0.0;
-        }
         st->Pt[0][i * s + j] = f;
-        st->Pt[1][i * s + j] = t;
       }
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) st->Pt[1][i * s + j] = st->Pt[0][j * s + i];
     for (int i = 0; i < s; ++i) st->pd[i] = st->Pt[0][i * s + i];
   }
   st->ia = o.splitting == IRK_SPLIT_IA;

@@ -69,8 +69,8 @@ def test_block_preconditioner(kind, pc, transpose, tname, N):
     ptab = {"radau3": P.tableaux.radau_iia(3), "gl4": P.tableaux.gauss_legendre(4),
             "radau2": P.tableaux.radau_iia(2)}[tname]
     s = otab["A"].shape[0]
-    A = otab["A"].T if transpose else otab["A"]
-    Atil = mg.preconditioner_matrix(kind, A)
+    A = otab["A"]
+    Atil = mg.preconditioner_matrix(kind, A)  # the transposed system uses Atil^T: the same diagonal blocks
     hier = mg.Hierarchy(N, kap, dt)
     _, stp = make(N, kap, ptab, dt, precond=pc)
     for i in range(s):
@@ -79,7 +79,7 @@ def test_block_preconditioner(kind, pc, transpose, tname, N):
         assert rel(host(stp.vcycle(i, dev(t))), hier.vcycle(Atil[i, i], t)) < 1e-12
     v = synth.random_stage_block(N, s, 11).ravel()
     z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
-    ref = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.vcycle_block_solver(hier, Atil))
+    ref = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.vcycle_block_solver(hier, Atil), trans=transpose)
     assert rel(z, ref) < 1e-12
 
 
@@ -97,11 +97,12 @@ def test_ia_block_preconditioner(kind, pc, transpose, tname, N):
     ptab = {"radau3": P.tableaux.radau_iia(3), "gl4": P.tableaux.gauss_legendre(4),
             "radau2": P.tableaux.radau_iia(2)}[tname]
     s = otab["A"].shape[0]
-    A = otab["A"].T if transpose else otab["A"]
+    A = otab["A"]
     Atil = mg.preconditioner_matrix(kind, A)
     hier = mg.Hierarchy(N, kap, dt)
     _, stp = make(N, kap, ptab, dt, precond=pc, splitting=P.SPLIT_IA)
     v = synth.random_stage_block(N, s, 13).ravel()
     z = host(stp.apply_preconditioner(dev(v), transpose=transpose))
-    ref = mg.apply_ia_block_preconditioner(kind, A, dt, M, K, v, mg.vcycle_ia_block_solver(hier, Atil))
+    ref = mg.apply_ia_block_preconditioner(kind, A, dt, M, K, v, mg.vcycle_ia_block_solver(hier, Atil),
+                                           trans=transpose)
     assert rel(z, ref) < 1e-12

@@ -181,6 +181,9 @@ def test_dirk_gs_lower_with_exact_blocks_converges_in_one_iteration():
         assert stp.levels == 1
         _, stats = stp.solve_stages(dev(f))
         assert 1 <= stats["fgmres_its_total"] <= its
+        # the transposed system is preconditioned by the transpose of P_L, exact here as well
+        _, stats = stp.solve_stages(dev(f), transpose=True)
+        assert 1 <= stats["fgmres_its_total"] <= its
         # s = 1 (backward Euler) with P_D likewise
         _, stp1 = make(N, kap, P.tableaux.radau_iia(1), dt, precond=P.PC_JACOBI, rtol=1e-12, orth=orth)
         _, stats = stp1.solve_stages(dev(f[: (N - 1) ** 2]))

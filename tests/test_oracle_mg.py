@@ -140,9 +140,11 @@ def test_ldu_factorisation():
     assert D[0] == 2.0 and D[1] == 5.0 - 4.0 * 1.0 / 2.0 and L1[1, 0] == 2.0 and U1[0, 1] == 0.5
 
 
+@pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("kind", ["jacobi", "gs_lower", "gs_upper", "rana_ld"])
-def test_exact_block_preconditioner_definition(kind):
-    # with exact blocks, P^{-1} v solves I (x) M + dt Atil (x) K with Atil = D, L + D or L1 D
+def test_exact_block_preconditioner_definition(kind, trans):
+    # with exact blocks, P^{-1} v solves I (x) M + dt Atil (x) K with Atil = D, L + D or L1 D; the transposed
+    # system's preconditioner is the transpose of that matrix
     N, dt = 10, 1e-2
     kap = synth.grf_kappa(N, 4)
     M, K = fem.assemble(N, kap)
@@ -151,8 +153,10 @@ def test_exact_block_preconditioner_definition(kind):
     Atil = {"jacobi": np.diag(np.diag(A)), "gs_lower": np.tril(A), "gs_upper": np.triu(A),
             "rana_ld": L1 @ np.diag(D)}[kind]
     v = np.random.default_rng(5).standard_normal(3 * (N - 1) ** 2)
-    z = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.exact_block_solver(M, K, Atil, dt))
+    z = mg.apply_block_preconditioner(kind, A, dt, K, v, mg.exact_block_solver(M, K, Atil, dt), trans=trans)
     P = _block_prec_matrix(M, K, Atil, dt)
+    if trans:
+        P = P.T
     assert np.linalg.norm(P @ z - v) < 1e-12 * np.linalg.norm(v)
 
 
@@ -173,13 +177,19 @@ def test_gs_lower_is_exact_for_dirk():
     # P_LD is exact for a DIRK too: A = L1 D with U1 = I
     zr = mg.apply_block_preconditioner("rana_ld", A, dt, K, Acal @ x, mg.exact_block_solver(M, K, A, dt))
     assert np.linalg.norm(zr - x) < 1e-12 * np.linalg.norm(x)
+    # the transpose of P_L (or P_LD) is the transposed operator itself: exact by backward substitution
+    for kind in ("gs_lower", "rana_ld"):
+        z2 = mg.apply_block_preconditioner(kind, A, dt, K, AcalT @ x, mg.exact_block_solver(M, K, A, dt),
+                                           trans=True)
+        assert np.linalg.norm(z2 - x) < 1e-12 * np.linalg.norm(x)
 
 
 # ---------------------------------------------------------------- IA-form preconditioners
 
 
+@pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("kind", ["jacobi", "gs_lower", "gs_upper", "rana_ld"])
-def test_exact_ia_block_preconditioner_definition(kind):
+def test_exact_ia_block_preconditioner_definition(kind, trans):
     # with exact blocks, P^{-1} v solves Atil^{-1} (x) M + dt I (x) K, and equals the AI-form
     # preconditioner applied to (Atil (x) I) v since P_IA = (Atil^{-1} (x) I) P_AI
     N, dt = 10, 1e-2
@@ -191,11 +201,16 @@ def test_exact_ia_block_preconditioner_definition(kind):
             "rana_ld": L1 @ np.diag(D)}[kind]
     n = (N - 1) ** 2
     v = np.random.default_rng(5).standard_normal(3 * n)
-    z = mg.apply_ia_block_preconditioner(kind, A, dt, M, K, v, mg.exact_ia_block_solver(M, K, Atil, dt))
+    z = mg.apply_ia_block_preconditioner(kind, A, dt, M, K, v, mg.exact_ia_block_solver(M, K, Atil, dt),
+                                         trans=trans)
     P = step.coupled_matrix_ia(M, K, Atil, dt)
+    if trans:
+        P = P.T
     assert np.linalg.norm(P @ z - v) < 1e-12 * np.linalg.norm(v)
-    mixed = (Atil @ v.reshape(3, -1)).ravel()
-    z_ai = mg.apply_block_preconditioner(kind, A, dt, K, mixed, mg.exact_block_solver(M, K, Atil, dt))
+    At = Atil.T if trans else Atil
+    mixed = (At @ v.reshape(3, -1)).ravel()
+    z_ai = mg.apply_block_preconditioner(kind, A, dt, K, mixed, mg.exact_block_solver(M, K, Atil, dt),
+                                         trans=trans)
     assert np.linalg.norm(z - z_ai) < 1e-12 * np.linalg.norm(z)
 
 
