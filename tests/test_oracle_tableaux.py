@@ -70,7 +70,7 @@ def test_alexander_order3_and_l_stable():
     assert abs(b @ c**2 - 1 / 3) < 1e-14
     assert abs(b @ A @ c - 1 / 6) < 1e-14
     assert abs(T.stability_function(tab, -1e12)[0]) < 1e-9
-    # the surveyed values of x, y, z
+    # x (the root of the cubic above in (1/6, 1/2)) and the last row of A, to ten digits
     assert abs(x - 0.4358665215) < 1e-10 and abs(A[2, 0] - 1.2084966492) < 1e-9
     assert abs(A[2, 1] + 0.6443631707) < 1e-9
 
