@@ -79,7 +79,8 @@ enum { IRK_STAGE_COUPLED = 0, IRK_STAGE_DIRK = 1 };
 /* Arnoldi steps queued ahead of the host's convergence test (IRK_ORTH_DCGS2 only). OFF queues each
  * step after the host has read the previous one. ADAPTIVE (default) queues step 0 before the host reads
  * the initial norms, and step j+2 behind step j+1 while the last residual reduction factor, applied once
- * more, leaves the estimate above 4x the target. ALWAYS queues step j+2 whenever the cycle has one. A step
+ * more, leaves the estimate above 4x the target (and step 1 with step 0 when the last solve of the same
+ * system took three or more iterations). ALWAYS queues step j+2 whenever the cycle has one. A step
  * queued ahead and not used writes only Krylov vectors the solution does not depend on, so all three give
  * bit-identical results; irk_stats.arnoldi_discarded counts such steps. */
 enum { IRK_LOOKAHEAD_OFF = 0, IRK_LOOKAHEAD_ADAPTIVE = 1, IRK_LOOKAHEAD_ALWAYS = 2 };

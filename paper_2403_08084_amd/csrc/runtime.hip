@@ -137,6 +137,7 @@ struct irk_stepper {
   double* hmir_dev = nullptr;  // its device address
   hipEvent_t step_ev[2] = {nullptr, nullptr};  // recorded on the solver's stream after step j
   hipEvent_t norm_ev = nullptr;                // behind the initial norms of a solve
+  int last_its[2 + kMaxStages] = {};           // iterations of the last solve per system (as graphs[])
   // measurement hook: events around every launch of one kernel family (eager launches only)
   int timer_family = -1;
   std::vector<hipEvent_t> timer_ev;       // pairs (start, end)
@@ -1001,21 +1002,27 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
   HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(st->norm_ev, s));
   const int look = st->opt.lookahead;
+  // step 1 goes in with step 0 when the last solve of this system needed three or more iterations
+  const int key = st->sys >= 0 ? 2 + st->sys : (trans ? 1 : 0);
+  const bool two = m > 1 && st->opt.max_it >= 2 &&
+                   (look == IRK_LOOKAHEAD_ALWAYS || (look == IRK_LOOKAHEAD_ADAPTIVE && st->last_its[key] >= 3));
   bool step0_queued = look != IRK_LOOKAHEAD_OFF;
   if (step0_queued) CHK(launch_step(0));
+  if (step0_queued && two) CHK(launch_step(1));
   HIPCHK(hipEventSynchronize(st->norm_ev));
   const double fnorm = std::sqrt(h[0]);
   if (!std::isfinite(fnorm)) return fail(IRK_EBREAKDOWN, "non-finite right-hand side");
   if (fnorm == 0.0) {
     HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    info.discarded = step0_queued ? 1 : 0;
+    info.discarded = step0_queued ? (two ? 2 : 1) : 0;
     return IRK_OK;
   }
   double beta = use_guess ? std::sqrt(h[1]) : fnorm;
   const double target = st->opt.rtol * fnorm;
   if (beta <= target) {
     info.rel = beta / fnorm;
-    info.discarded = step0_queued ? 1 : 0;
+    info.discarded = step0_queued ? (two ? 2 : 1) : 0;
+    st->last_its[key] = 0;
     return IRK_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m), y(m);
@@ -1024,9 +1031,13 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
     double g0 = beta;
     int jdone = 0;
     double est_prev = beta;
-    if (!step0_queued) CHK(launch_step(0));
-    step0_queued = false;
     int launched = 0;  // highest step enqueued in this cycle
+    if (step0_queued) {
+      launched = two ? 1 : 0;
+    } else {
+      CHK(launch_step(0));
+    }
+    step0_queued = false;
     int read = 0;      // highest step whose reduction the host has taken
     for (int j = 0; j < m; ++j) {
       HIPCHK(hipEventSynchronize(st->step_ev[j & 1]));
@@ -1100,6 +1111,7 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
     beta = std::sqrt(h[0]);
     info.rel = beta / fnorm;
     if (!std::isfinite(beta)) return fail(IRK_EBREAKDOWN, "non-finite residual in FGMRES");
+    st->last_its[key] = info.its;
     if (beta <= target) return IRK_OK;
     if (info.its >= st->opt.max_it) {
       char buf[160];
