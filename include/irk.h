@@ -60,7 +60,7 @@ typedef enum {
 } irk_status;
 
 /* eq:pcbjac, eq:pcbgs, eq:pcranald, the block upper-triangular variant of eq:pcbgs (Section 3.1),
- * and one monolithic multigrid V-cycle on the whole stage-coupled system (Section 3.3) */
+ * and one monolithic multigrid V-cycle on the whole stage-coupled system (Section 3.2) */
 enum { IRK_PC_JACOBI = 0, IRK_PC_GS_LOWER = 1, IRK_PC_RANA_LD = 2, IRK_PC_GS_UPPER = 3, IRK_PC_MONOLITHIC = 4 };
 enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precision */
 /* Gram-Schmidt variant of the Arnoldi process: classical with re-orthogonalisation (three passes per
@@ -68,7 +68,7 @@ enum { IRK_F64 = 0, IRK_F32 = 1, IRK_BF16 = 2 };            /* multigrid precisi
  * Swirydowicz et al., Numer. Linear Algebra Appl. 2021) */
 enum { IRK_ORTH_CGS2 = 0, IRK_ORTH_CGS_SELECTIVE = 1, IRK_ORTH_DCGS2 = 2 };
 enum { IRK_GUESS_ZERO = 0, IRK_GUESS_PREV = 1 };            /* FGMRES initial guess */
-/* Stage formulation (Section 2.4): AI solves eq:block_struct_AI for the stage derivatives k;
+/* Stage formulation (Section 2.2): AI solves eq:block_struct_AI for the stage derivatives k;
  * IA solves eq:block_struct_IA, (A^{-1} (x) M + dt I (x) K) w = f, for w = (A (x) I) k
  * (eq:butcherw, eq:stageeqw); A must then be invertible. */
 enum { IRK_SPLIT_AI = 0, IRK_SPLIT_IA = 1 };
@@ -137,10 +137,12 @@ const char *irk_last_error(void);
 
 /* Defaults: GS_LOWER, rtol 1e-10, restart 30, max_it 300, coarse 32, Chebyshev
  * degree 2 on [0.25 mu, 1.1 mu] (the interval of Section 4.3), 15 power
- * iterations, FP64 multigrid, CGS2, zero initial guess, graphs on. */
+ * iterations, FP64 multigrid, DCGS2 (delayed one-reduction CGS2), zero initial
+ * guess, graphs on, AI splitting, coupled stage solve, ADAPTIVE lookahead. */
 void irk_options_default(irk_options *opts);
 
-/* Problem: the grid and the diffusivity. N >= 2 elements per side; kappa is a
+/* Problem (Section 2, eq:rkheat with the Q1 discretisation of div(kappa grad u) on the
+ * unit square): the grid and the diffusivity. N >= 2 elements per side; kappa is a
  * device array of N*N doubles (element layout), copied; every entry must be
  * finite and > 0 (IRK_EINVAL otherwise). The multigrid halves N while it is even
  * and above mg_coarse_n; the coarsest level Nc needs (Nc-1)^2 <= 1024 (dense solve),
@@ -148,13 +150,18 @@ void irk_options_default(irk_options *opts);
 int irk_problem_create(irk_problem **out, int N, const double *kappa, void *stream);
 void irk_problem_destroy(irk_problem *p);
 
-/* y = M x on one nodal vector (device, n doubles each; x and y must not overlap). */
+/* y = M x on one nodal vector: the consistent mass matrix M of eq:rkheat (Section 2),
+ * Dirichlet rows and columns removed (device, n doubles each; x and y must not overlap).
+ * Used for objectives such as J = 1/2 |u - u_*|_M^2. */
 int irk_apply_mass(const irk_problem *p, const double *x, double *y, void *stream);
 
-/* y = K x (device, n doubles each; no overlap). */
+/* y = K x: the stiffness matrix K of eq:rkheat (Section 2) with the problem's kappa,
+ * Dirichlet rows and columns removed (device, n doubles each; no overlap). */
 int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *stream);
 
-/* Stepper: a tableau, a time step and solver options on a problem; sets up the
+/* Stepper (Section 2 time stepping of eq:rkheat with the stage system eq:block_struct_AI or
+ * eq:block_struct_IA and a Section 3 preconditioner): a tableau, a time step and solver
+ * options on a problem; sets up the
  * multigrid hierarchy (level diffusivities, power-iteration estimates of mu per
  * level and diagonal block, the coarsest-level inverse) and the Krylov
  * workspace. Every eigenvalue of A must have positive real part and every
@@ -178,7 +185,7 @@ int irk_apply_stage_operator(const irk_stepper *st, const double *x, double *y, 
  * P = I (x) M + dt Atil (x) K, stages coupled through K. IA splitting (the printed form):
  * P = Atil^{-1} (x) M + dt I (x) K, stages coupled through M, diagonal blocks
  * (1/atil_ii) M + dt K, whose V-cycle is atil_ii times the V-cycle of M + dt atil_ii K.
- * IRK_PC_MONOLITHIC: one monolithic V-cycle (Section 3.3, eq:Cinv on the patches of
+ * IRK_PC_MONOLITHIC: one monolithic V-cycle (Section 3.2, eq:Cinv on the patches of
  * eq:bigdecomp) on the whole system: additive Schwarz over each vertex's s stage values
  * (an s x s solve per node) inside Chebyshev smoothing, stage-wise transfers, a dense
  * solve on the coarsest level (halving while N is even and N > mg_coarse_n or

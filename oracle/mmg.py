@@ -1,4 +1,4 @@
-"""Monolithic multigrid for the stage-coupled system (Section 3.3), plain CSR statement (FP64, CPU).
+"""Monolithic multigrid for the stage-coupled system (Section 3.2), plain CSR statement (FP64, CPU).
 
 Test infrastructure only (see the package docstring).
 

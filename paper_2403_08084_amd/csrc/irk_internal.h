@@ -71,7 +71,7 @@ struct MGCoef {
   int deg;
 };
 
-// One level of the monolithic cycle (Section 3.3): operator cm (x) M + dt ck (x) K on s planes,
+// One level of the monolithic cycle (Section 3.2): operator cm (x) M + dt ck (x) K on s planes,
 // additive Schwarz patch blocks cm M_vv + dt ck K_vv, Chebyshev coefficients as in MGCoef.
 struct MMGCoef {
   int s;

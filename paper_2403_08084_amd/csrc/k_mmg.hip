@@ -1,4 +1,4 @@
-// Monolithic multigrid kernels for the stage-coupled operator (Section 3.3).
+// Monolithic multigrid kernels for the stage-coupled operator (Section 3.2).
 //
 // A level operator acts on s stage planes at once,
 //   (Acal x)_q = sum_r cm[q][r] M x_r + dt * sum_r ck[q][r] K x_r,
@@ -6,8 +6,11 @@
 // for the adjoint). The relaxation is additive Schwarz over the vertex patches of all
 // stages (eq:Cinv, eq:bigdecomp): at every interior node the s x s patch block
 //   C_v = cm * M_vv + dt * ck * K_vv,   M_vv = 16 h^2/36,  K_vv = (2/3) * (sum of the 4 kappa),
-// is solved in registers (Gaussian elimination with partial pivoting), inside a Chebyshev
-// iteration. One thread owns one node and all of its stages, so the s x s stage mixing
+// is solved in registers inside a Chebyshev iteration. Every patch block has the form
+// (1/w)(I + tau B) with one fixed s x s matrix B per level and a scalar tau from the node's
+// diffusivity, so its inverse is applied in closed form, w adj(I + tau B) / det(I + tau B), with the
+// adjugate and determinant as polynomials in tau whose coefficients the host computes once per level
+// (Faddeev-LeVerrier). One thread owns one node and all of its stages, so the s x s stage mixing
 // never leaves registers.
 //
 // Kernels per level of a V-cycle: a fused DOWN (pre-smoothing, residual, restriction) and a

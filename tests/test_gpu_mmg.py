@@ -1,4 +1,4 @@
-"""GPU parity: the monolithic multigrid cycle (Section 3.3) vs the oracle's CSR statement (oracle.mmg), and the
+"""GPU parity: the monolithic multigrid cycle (Section 3.2) vs the oracle's CSR statement (oracle.mmg), and the
 FGMRES solves and time steps it preconditions."""
 import numpy as np
 import pytest
@@ -84,7 +84,7 @@ def test_mmg_advance_matches_oracle(prec, tol):
 
 
 def test_mmg_iterations_nearly_flat_in_stages():
-    # Section 3.3: the monolithic cycle's convergence does not depend explicitly on the number of stages
+    # Section 3.2: the monolithic cycle's convergence does not depend explicitly on the number of stages
     N, dt = 128, 1e-3
     kap = synth.grf_kappa(N, 1)
     u0, _ = synth.sine_modes_u0(N, 0)
