@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libirk.so")
-SOURCES = ["k_stencil.hip", "k_mg.hip", "k_mmg.hip", "k_krylov.hip", "runtime.hip"]
+SOURCES = ["k_stencil.hip", "k_mg.hip", "k_mmg.hip", "k_krylov.hip", "runtime.hip", "host_math.cpp"]
 
 ARCH = os.environ.get("IRK_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

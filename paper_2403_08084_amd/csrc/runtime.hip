@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/irk.h"
+#include "host_math.h"
 #include "irk_internal.h"
 
 using namespace irk;
@@ -194,38 +195,6 @@ Coefs b_of(const irk_stepper* st) {
   return b;
 }
 
-// inverse of a small dense row-major s x s matrix by Gauss-Jordan elimination with partial
-// pivoting; false if a pivot is negligible against the matrix norm
-bool small_inverse(const double* A, int s, double* inv) {
-  double W[kMaxStages * 2 * kMaxStages];
-  double nrm = 0;
-  for (int i = 0; i < s; ++i)
-    for (int j = 0; j < s; ++j) {
-      W[i * 2 * s + j] = A[i * s + j];
-      W[i * 2 * s + s + j] = (i == j) ? 1.0 : 0.0;
-      nrm = std::max(nrm, std::fabs(A[i * s + j]));
-    }
-  for (int k = 0; k < s; ++k) {
-    int pr = k;
-    for (int i = k + 1; i < s; ++i)
-      if (std::fabs(W[i * 2 * s + k]) > std::fabs(W[pr * 2 * s + k])) pr = i;
-    if (!(std::fabs(W[pr * 2 * s + k]) > 1e-13 * nrm)) return false;
-    if (pr != k)
-      for (int j = 0; j < 2 * s; ++j) std::swap(W[k * 2 * s + j], W[pr * 2 * s + j]);
-    const double d = W[k * 2 * s + k];
-    for (int j = 0; j < 2 * s; ++j) W[k * 2 * s + j] /= d;
-    for (int i = 0; i < s; ++i) {
-      if (i == k) continue;
-      const double f = W[i * 2 * s + k];
-      if (f != 0.0)
-        for (int j = 0; j < 2 * s; ++j) W[i * 2 * s + j] -= f * W[k * 2 * s + j];
-    }
-  }
-  for (int i = 0; i < s; ++i)
-    for (int j = 0; j < s; ++j) inv[i * s + j] = W[i * 2 * s + s + j];
-  return true;
-}
-
 // ------------------------------------------------------------------ reductions
 
 // Next (start, end) event pair of the measurement hook, or nulls when the family is not timed.
@@ -307,21 +276,8 @@ int dot(irk_stepper* st, const double* x, const double* y, long len, double* res
 // ------------------------------------------------------------------ multigrid setup
 
 void cheb_coef(double mu, const irk_options& o, MGCoef& c) {
-  const double lo = o.cheb_lo * mu, hi = o.cheb_hi * mu;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   c.deg = o.cheb_degree;
-  c.c0 = 1.0 / theta;
-  double rho = 1.0 / sigma;
-  for (int k = 0; k < kMaxDeg; ++k) {
-    c.beta[k] = 0.0;
-    c.gam[k] = 0.0;
-  }
-  for (int k = 1; k < o.cheb_degree; ++k) {
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    c.beta[k] = rn * rho;
-    c.gam[k] = 2.0 * rn / delta;
-    rho = rn;
-  }
+  host::chebyshev_coefficients(o.cheb_lo * mu, o.cheb_hi * mu, o.cheb_degree, kMaxDeg, &c.c0, c.beta, c.gam);
 }
 
 // Largest eigenvalue of D^{-1}B on one level by power iteration from the SplitMix64 start vector.
@@ -356,57 +312,15 @@ int power_mu(irk_stepper* st, int level, double alpha, double* mu_out, hipStream
   return IRK_OK;
 }
 
-// Dense inverse of the coarsest-level block M + alpha*K (interior nodes), by Cholesky.
+// Dense inverse of the coarsest-level block M + alpha*K (interior nodes): banded Cholesky (half-bandwidth N)
 int coarse_inverse(const std::vector<double>& kap, int N, double alpha, std::vector<double>& inv) {
   const int m = N - 1, n = m * m;
-  const double h = 1.0 / N;
-  const double Kr[4][4] = {{4, -1, -2, -1}, {-1, 4, -1, -2}, {-2, -1, 4, -1}, {-1, -2, -1, 4}};
-  const double Mr[4][4] = {{4, 2, 1, 2}, {2, 4, 2, 1}, {1, 2, 4, 2}, {2, 1, 2, 4}};
-  const int dx[4] = {0, 1, 1, 0}, dy[4] = {0, 0, 1, 1};
-  std::vector<double> B((size_t)n * n, 0.0);
-  for (int ey = 0; ey < N; ++ey)
-    for (int ex = 0; ex < N; ++ex) {
-      int idx[4];
-      for (int a = 0; a < 4; ++a) {
-        const int i = ex + dx[a], j = ey + dy[a];
-        idx[a] = (i >= 1 && i <= m && j >= 1 && j <= m) ? (j - 1) * m + (i - 1) : -1;
-      }
-      const double ke = kap[(size_t)ey * N + ex];
-      for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c)
-          if (idx[a] >= 0 && idx[c] >= 0)
-            B[(size_t)idx[a] * n + idx[c]] += alpha * ke * Kr[a][c] / 6.0 + h * h * Mr[a][c] / 36.0;
-    }
-  // Cholesky B = L L^T (lower, in place)
-  for (int j = 0; j < n; ++j) {
-    double d = B[(size_t)j * n + j];
-    for (int k2 = 0; k2 < j; ++k2) d -= B[(size_t)j * n + k2] * B[(size_t)j * n + k2];
-    if (!(d > 0)) return fail(IRK_EINVAL, "coarsest-level block is not positive definite");
-    d = std::sqrt(d);
-    B[(size_t)j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double v = B[(size_t)i * n + j];
-      for (int k2 = 0; k2 < j; ++k2) v -= B[(size_t)i * n + k2] * B[(size_t)j * n + k2];
-      B[(size_t)i * n + j] = v / d;
-    }
-  }
+  std::vector<double> K((size_t)n * n, 0.0), B((size_t)n * n, 0.0);
+  host::assemble_q1(kap.data(), N, N, K.data(), B.data());
+  for (size_t q = 0; q < B.size(); ++q) B[q] += alpha * K[q];
   inv.assign((size_t)n * n, 0.0);
-  std::vector<double> col(n);
-  for (int c = 0; c < n; ++c) {
-    std::fill(col.begin(), col.end(), 0.0);
-    col[c] = 1.0;
-    for (int i = 0; i < n; ++i) {  // L y = e_c
-      double v = col[i];
-      for (int k2 = 0; k2 < i; ++k2) v -= B[(size_t)i * n + k2] * col[k2];
-      col[i] = v / B[(size_t)i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {  // L^T x = y
-      double v = col[i];
-      for (int k2 = i + 1; k2 < n; ++k2) v -= B[(size_t)k2 * n + i] * col[k2];
-      col[i] = v / B[(size_t)i * n + i];
-    }
-    for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = col[i];
-  }
+  if (host::spd_band_inverse(B.data(), n, m + 1, inv.data()) != 0)
+    return fail(IRK_EINVAL, "coarsest-level block is not positive definite");
   return IRK_OK;
 }
 
@@ -508,38 +422,6 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
 
 // ------------------------------------------------------------------ monolithic multigrid setup
 
-// dense inverse of a general n x n row-major matrix (Gauss-Jordan with partial pivoting)
-int dense_inverse(std::vector<double>& W, int n, std::vector<double>& inv) {
-  inv.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
-  for (int k = 0; k < n; ++k) {
-    int pr = k;
-    for (int i = k + 1; i < n; ++i)
-      if (std::fabs(W[(size_t)i * n + k]) > std::fabs(W[(size_t)pr * n + k])) pr = i;
-    if (!(std::fabs(W[(size_t)pr * n + k]) > 0)) return fail(IRK_EINVAL, "singular coarsest coupled operator");
-    if (pr != k)
-      for (int j = 0; j < n; ++j) {
-        std::swap(W[(size_t)k * n + j], W[(size_t)pr * n + j]);
-        std::swap(inv[(size_t)k * n + j], inv[(size_t)pr * n + j]);
-      }
-    const double d = 1.0 / W[(size_t)k * n + k];
-    for (int j = 0; j < n; ++j) {
-      W[(size_t)k * n + j] *= d;
-      inv[(size_t)k * n + j] *= d;
-    }
-    for (int i = 0; i < n; ++i) {
-      if (i == k) continue;
-      const double f = W[(size_t)i * n + k];
-      if (f == 0.0) continue;
-      for (int j = 0; j < n; ++j) {
-        W[(size_t)i * n + j] -= f * W[(size_t)k * n + j];
-        inv[(size_t)i * n + j] -= f * inv[(size_t)k * n + j];
-      }
-    }
-  }
-  return IRK_OK;
-}
-
 // the level operator's stage mixing: AI (I, Op), IA (Op, I), with Op = A, A^T or A^{-1}, A^{-T}
 void mmg_mixing(const irk_stepper* st, int trans, MMGCoef& c) {
   const int s = st->s;
@@ -549,33 +431,12 @@ void mmg_mixing(const irk_stepper* st, int trans, MMGCoef& c) {
       c.cm[q * kMMGMax + r] = st->ia ? op : id;
       c.ck[q * kMMGMax + r] = st->ia ? id : op;
     }
-  // closed form of the patch-block inverse: with B = Op, adj(I + tau B) = sum_k (-tau)^k N_k and
-  // det(I + tau B) = sum_k c_k (-tau)^k, where N_0 = I, c_k = -tr(B N_{k-1}) / k, N_k = B N_{k-1} + c_k I
+  // closed form of the patch-block inverse: adj(I + tau B) and det(I + tau B) as polynomials in tau for B = Op
   // (Faddeev-LeVerrier recursion for the characteristic polynomial and adjugate of B)
-  double N[kMMGMax * kMMGMax], BN[kMMGMax * kMMGMax];
-  for (int i = 0; i < kMMGMax * kMMGMax; ++i) N[i] = 0.0;
-  for (int i = 0; i < s; ++i) N[i * kMMGMax + i] = 1.0;
-  for (int i = 0; i < kMMGMax * kMMGMax * kMMGMax; ++i) c.adj[i] = 0.0;
-  for (int i = 0; i <= kMMGMax; ++i) c.det[i] = 0.0;
-  c.det[0] = 1.0;
-  double sign = 1.0;
-  for (int k = 0; k < s; ++k) {
-    for (int i = 0; i < s * kMMGMax; ++i) c.adj[k * kMMGMax * kMMGMax + i] = sign * N[i];
-    // BN = B N_k, c_{k+1} = -tr(BN)/(k+1), N_{k+1} = BN + c_{k+1} I
-    double tr = 0.0;
-    for (int i = 0; i < s; ++i)
-      for (int j = 0; j < s; ++j) {
-        double acc = 0.0;
-        for (int l = 0; l < s; ++l) acc += st->Op[trans][i * s + l] * N[l * kMMGMax + j];
-        BN[i * kMMGMax + j] = acc;
-      }
-    for (int i = 0; i < s; ++i) tr += BN[i * kMMGMax + i];
-    const double ck = -tr / (k + 1);
-    sign = -sign;
-    c.det[k + 1] = sign * ck;
-    for (int i = 0; i < s; ++i)
-      for (int j = 0; j < s; ++j) N[i * kMMGMax + j] = BN[i * kMMGMax + j] + (i == j ? ck : 0.0);
-  }
+  double B[kMMGMax * kMMGMax] = {};
+  for (int q = 0; q < s; ++q)
+    for (int r = 0; r < s; ++r) B[q * kMMGMax + r] = st->Op[trans][q * s + r];
+  host::faddeev_leverrier(B, s, kMMGMax, c.adj, c.det);
   c.ia = st->ia ? 1 : 0;
   const double mv = 16.0 * c.m;  // M_vv
   c.tfac = st->ia ? mv / st->dt : st->dt / mv;
@@ -688,27 +549,7 @@ int setup_mmg(irk_stepper* st, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(kpad.data(), lc.kap64, kpad.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<double> Mc((size_t)nc * nc, 0.0), Kc((size_t)nc * nc, 0.0);
-  {
-    const double h = 1.0 / N;
-    const double Kr[4][4] = {{4, -1, -2, -1}, {-1, 4, -1, -2}, {-2, -1, 4, -1}, {-1, -2, -1, 4}};
-    const double Mr[4][4] = {{4, 2, 1, 2}, {2, 4, 2, 1}, {1, 2, 4, 2}, {2, 1, 2, 4}};
-    const int dx[4] = {0, 1, 1, 0}, dy[4] = {0, 0, 1, 1};
-    for (int ey = 0; ey < N; ++ey)
-      for (int ex = 0; ex < N; ++ex) {
-        int idx[4];
-        for (int a = 0; a < 4; ++a) {
-          const int i = ex + dx[a], j = ey + dy[a];
-          idx[a] = (i >= 1 && i <= m && j >= 1 && j <= m) ? (j - 1) * m + (i - 1) : -1;
-        }
-        const double ke = kpad[(size_t)ey * lc.g.pitch + ex];
-        for (int a = 0; a < 4; ++a)
-          for (int c = 0; c < 4; ++c)
-            if (idx[a] >= 0 && idx[c] >= 0) {
-              Kc[(size_t)idx[a] * nc + idx[c]] += ke * Kr[a][c] / 6.0;
-              Mc[(size_t)idx[a] * nc + idx[c]] += h * h * Mr[a][c] / 36.0;
-            }
-      }
-  }
+  host::assemble_q1(kpad.data(), lc.g.pitch, N, Kc.data(), Mc.data());
   const MMGCoef& c0 = st->mcoef[0][L - 1];
   std::vector<double> W((size_t)n * n, 0.0), inv;
   for (int q = 0; q < ns; ++q)
@@ -719,7 +560,8 @@ int setup_mmg(irk_stepper* st, hipStream_t s) {
         for (int j = 0; j < nc; ++j)
           W[(size_t)(q * nc + i) * n + r * nc + j] = a * Mc[(size_t)i * nc + j] + b * Kc[(size_t)i * nc + j];
     }
-  CHK(dense_inverse(W, n, inv));
+  inv.assign((size_t)n * n, 0.0);
+  if (host::dense_inverse(W.data(), n, inv.data()) != 0) return fail(IRK_EINVAL, "singular coarsest coupled operator");
   for (int tr = 0; tr < 2; ++tr) {
     std::vector<double> use(inv.size());
     for (int i = 0; i < n; ++i)
@@ -944,34 +786,6 @@ struct SolveInfo {
   int discarded = 0;  // Arnoldi steps launched ahead of the host's decision and not used
 };
 
-// Least-squares estimate of FGMRES with the (ncol+1) x ncol Hessenberg H (row stride m): Givens QR from
-// scratch; returns |g_ncol| and, if y is given, the solution of R y = g.
-double hessenberg_ls(const std::vector<double>& H, int m, int ncol, double g0, double* y) {
-  std::vector<double> R(H.begin(), H.begin() + (size_t)(ncol + 1) * m), g(ncol + 1, 0.0);
-  g[0] = g0;
-  for (int j = 0; j < ncol; ++j) {
-    const double a = R[(size_t)j * m + j], b = R[(size_t)(j + 1) * m + j];
-    const double r = std::hypot(a, b);
-    const double c = r > 0 ? a / r : 1.0, sn = r > 0 ? b / r : 0.0;
-    for (int k = j; k < ncol; ++k) {
-      const double t0 = c * R[(size_t)j * m + k] + sn * R[(size_t)(j + 1) * m + k];
-      const double t1 = -sn * R[(size_t)j * m + k] + c * R[(size_t)(j + 1) * m + k];
-      R[(size_t)j * m + k] = t0;
-      R[(size_t)(j + 1) * m + k] = t1;
-    }
-    const double t0 = c * g[j] + sn * g[j + 1], t1 = -sn * g[j] + c * g[j + 1];
-    g[j] = t0;
-    g[j + 1] = t1;
-  }
-  if (y)
-    for (int i = ncol - 1; i >= 0; --i) {
-      double v = g[i];
-      for (int k = i + 1; k < ncol; ++k) v -= R[(size_t)i * m + k] * y[k];
-      y[i] = v / R[(size_t)i * m + i];
-    }
-  return std::fabs(g[ncol]);
-}
-
 // FGMRES with the delayed CGS2 Arnoldi process. The Hessenberg column of step j is provisional until
 // step j+1 re-orthogonalises and normalises the direction it produced: then the column gains the
 // re-orthogonalisation coefficients and its subdiagonal entry becomes that direction's exact norm
@@ -1069,7 +883,7 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
       H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(nu, 0.0));
       info.its++;
       jdone = j + 1;
-      const double est = hessenberg_ls(H, m, jdone, g0, nullptr);
+      const double est = host::hessenberg_ls(H.data(), m, jdone, g0, nullptr);
       if (est <= target || H[(size_t)(j + 1) * m + j] <= 1e-300 * std::fabs(hj)) break;
       if (info.its >= st->opt.max_it) break;
       if (j + 1 < m && launched == j) {
@@ -1090,7 +904,7 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
     }
     info.discarded += launched - read;
     if (jdone > 0) {
-      hessenberg_ls(H, m, jdone, g0, y.data());
+      host::hessenberg_ls(H.data(), m, jdone, g0, y.data());
       std::copy(y.begin(), y.begin() + jdone, h);
       HIPCHK(hipMemcpyAsync(ycoef_dev(st), h, jdone * sizeof(double), hipMemcpyHostToDevice, s));
       OrthoArgs ax = ortho_base();
@@ -1313,79 +1127,6 @@ int forward_step(irk_stepper* st, const double* Fp, SolveInfo& si, hipStream_t s
 }
 
 // ------------------------------------------------------------------ binomial checkpointing
-
-long binom_sat(long n, long k) {
-  if (k < 0 || k > n) return 0;
-  k = std::min(k, n - k);
-  double r = 1.0;
-  for (long i = 1; i <= k; ++i) {
-    r = r * (double)(n - k + i) / (double)i;
-    if (r > 4e18) return (long)4e18;
-  }
-  return (long)std::llround(r);
-}
-
-// minimal forward advances to reverse l steps with c slots (Griewank's binomial bound)
-long revolve_cost(long l, long c) {
-  if (l <= 1) return 0;
-  if (c <= 1) return l * (l - 1) / 2;
-  long r = 0;
-  while (binom_sat(c + r, c) < l) ++r;
-  return r * l - binom_sat(c + r, c + 1);
-}
-
-struct Action {
-  int kind, arg;
-};
-
-// reverse steps [a, a+l) with the state u_a in slot `slot`, `c` slots usable from `slot` on
-void revolve_rec(int a, int l, int c, int slot, int& cur, std::vector<Action>& out, long& adv) {
-  if (l <= 0) return;
-  if (l == 1) {
-    if (cur != a) out.push_back({2, slot});
-    cur = a;
-    out.push_back({3, a});
-    return;
-  }
-  if (c == 1) {
-    for (int stp = a + l - 1; stp >= a; --stp) {
-      if (cur != a) out.push_back({2, slot});
-      cur = a;
-      if (stp > a) {
-        out.push_back({0, stp - a});
-        adv += stp - a;
-        cur = stp;
-      }
-      out.push_back({3, stp});
-    }
-    return;
-  }
-  int best = 1;
-  long bestc = -1;
-  for (int k2 = 1; k2 < l; ++k2) {
-    const long cost = k2 + revolve_cost(l - k2, c - 1) + revolve_cost(k2, c);
-    if (bestc < 0 || cost < bestc) {
-      bestc = cost;
-      best = k2;
-    }
-  }
-  if (cur != a) out.push_back({2, slot});
-  out.push_back({0, best});
-  adv += best;
-  cur = a + best;
-  out.push_back({1, slot + 1});
-  revolve_rec(a + best, l - best, c - 1, slot + 1, cur, out, adv);
-  revolve_rec(a, best, c, slot, cur, out, adv);
-}
-
-std::vector<Action> revolve_schedule(int nsteps, int nsnap, long& adv) {
-  std::vector<Action> out;
-  adv = 0;
-  int cur = 0;
-  out.push_back({1, 0});
-  revolve_rec(0, nsteps, nsnap, 0, cur, out, adv);
-  return out;
-}
 
 int validate_stepper(const irk_stepper* st) {
   if (!st) return fail(IRK_EINVAL, "stepper is NULL");
@@ -1653,7 +1394,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   st->dirk = o.stage_type == IRK_STAGE_DIRK;
   {
     double Ainv[kMaxStages * kMaxStages];
-    if (st->ia && !small_inverse(tab->A, s, Ainv)) {
+    if (st->ia && !host::small_inverse(tab->A, s, Ainv)) {
       delete st;
       return fail(IRK_EINVAL, "the IA splitting needs an invertible A");
     }
@@ -1671,7 +1412,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
     }
     if (st->ia)
       for (int t = 0; t < 2; ++t)
-        if (!small_inverse(st->Pt[t], s, st->Ci[t])) {
+        if (!host::small_inverse(st->Pt[t], s, st->Ci[t])) {
           delete st;
           return fail(IRK_EINVAL, "singular preconditioner matrix");
         }
@@ -1866,7 +1607,7 @@ int irk_revolve_schedule(int nsteps, int nsnap, int* actions, int cap, int* coun
   g_err.clear();
   if (nsteps < 0 || nsnap < 1) return fail(IRK_EINVAL, "need nsteps >= 0 and nsnap >= 1");
   long adv = 0;
-  std::vector<Action> sch = revolve_schedule(nsteps, std::min(nsnap, std::max(nsteps, 1)), adv);
+  std::vector<host::Action> sch = host::revolve_schedule(nsteps, std::min(nsnap, std::max(nsteps, 1)), adv);
   if (count) *count = (int)sch.size();
   if (advances) *advances = (int)adv;
   if (!actions) return IRK_OK;
@@ -1914,13 +1655,13 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
   launch_pack(u0, st->u, g, 1, s);
   launch_pack(lambda_T, lam, g, 1, s);
   long adv = 0;
-  std::vector<Action> sch = revolve_schedule(nsteps, slots, adv);
+  std::vector<host::Action> sch = host::revolve_schedule(nsteps, slots, adv);
   const Coefs at = mix_of(st);
   const Coefs bb = b_of(st);
   st->have_prev = false;
   int done = 0;
   for (size_t q = 0; q < sch.size() && rc == IRK_OK; ++q) {
-    const Action& act = sch[q];
+    const host::Action& act = sch[q];
     if (act.kind == 0) {
       for (int r = 0; r < act.arg && rc == IRK_OK; ++r) {
         SolveInfo si;

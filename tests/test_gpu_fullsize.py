@@ -1,11 +1,14 @@
 """GPU parity at the full workload sizes, in the launch configuration bench.py times.
 
-Configs 3/4 (1024^2) are compared with the oracle's results stored by
-tests/golden/make_golden.py (norm, seeded samples, Gaussian sketch); config 2
-(512^2, kappa = 1) with the closed form at every step; config 5 (512^2 adjoint)
-with the oracle gradient and with central finite differences."""
+Configs 3/4 (1024^2, variable kappa) are compared node by node with the oracle's eigen-decoupled direct solve
+(oracle.step.DecoupledLU: the full coupled LU does not fit at 1024^2; the decoupled tier equals it to rounding,
+pinned at smaller sizes), computed once per session: the relative L2 error of the whole interior vector at every
+one of the 20 steps, maximised over the steps. Config 2 (512^2, kappa = 1) is compared with the closed form at
+every step; config 5 (512^2 adjoint) with the oracle gradient stored by tests/golden/make_golden.py and with
+central finite differences."""
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -18,6 +21,7 @@ from gpu_util import dev, host, make, rel
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+_ORACLE = {}
 
 
 def _load(name):
@@ -32,33 +36,40 @@ def _compare(u, ref, idx, G):
     return max(sketch, samples, abs(np.linalg.norm(u) - ref["norm2"]) / ref["norm2"])
 
 
-def _run_golden(g, tab, prec, pc, tol):
-    N = g["N"]
-    n = g["n"]
+def _oracle_states(tname, dt, nsteps, N=1024):
+    """[u^0 .. u^nsteps] of the workload (kappa = exp(GRF seed 1), 16 sine modes) from the decoupled direct tier."""
+    key = (tname, dt, nsteps, N)
+    if key not in _ORACLE:
+        tab = {"radau3": OT.radau_iia(3), "gl4": OT.gauss_legendre(4)}[tname]
+        t0 = time.time()
+        _ORACLE[key] = step.run(N, synth.grf_kappa(N, 1), tab, dt, nsteps, synth.sine_modes_u0(N, 0)[0],
+                                tier="decoupled")
+        print(f"oracle {tname} {N}^2 {nsteps} steps: {time.time() - t0:.1f} s", flush=True)
+    return _ORACLE[key]
+
+
+def _run_fullsize(tname, tab, dt, nsteps, prec, pc, tol, N=1024):
+    ref = _oracle_states(tname, dt, nsteps, N)
     kap = synth.grf_kappa(N, 1)
-    u0, _ = synth.sine_modes_u0(N, 0)
-    idx = np.asarray(g["indices"])
-    G = synth.sketch_vectors(n, g["n_sketch"], g["sketch_seed"])
-    _, stp = make(N, kap, tab, g["dt"], mg_precision=prec, precond=pc, rtol=1e-10)
-    u = dev(u0)
-    done = 0
-    errs = {}
-    for k in sorted(int(x) for x in g["steps"]):
-        stp.advance(u, k - done)
-        done = k
-        errs[k] = _compare(host(u), g["steps"][str(k)], idx, G)
-    assert max(errs.values()) < tol, errs
+    _, stp = make(N, kap, tab, dt, mg_precision=prec, precond=pc, rtol=1e-10)
+    u = dev(ref[0])
+    errs = []
+    for k in range(1, nsteps + 1):
+        stp.advance(u, 1)
+        errs.append(rel(host(u), ref[k]))
+    print(f"{tname} prec {prec} pc {pc}: max over steps {max(errs):.2e}, final {errs[-1]:.2e}")
+    assert max(errs) < tol, errs
     return errs
 
 
 @pytest.mark.parametrize("prec,tol", [(P.F64, 1e-10), (P.F32, 1e-8), (P.BF16, 1e-8)])
 def test_config4_fullsize(prec, tol):
-    _run_golden(_load("config4_radau3_1024.json"), P.tableaux.radau_iia(3), prec, P.PC_GS_LOWER, tol)
+    _run_fullsize("radau3", P.tableaux.radau_iia(3), 1e-3, 20, prec, P.PC_GS_LOWER, tol)
 
 
 @pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
 def test_config3_fullsize_gl4(pc):
-    _run_golden(_load("config3_gl4_1024.json"), P.tableaux.gauss_legendre(4), P.F64, pc, 1e-10)
+    _run_fullsize("gl4", P.tableaux.gauss_legendre(4), 5e-4, 20, P.F64, pc, 1e-10)
 
 
 def test_config2_fullsize_closed_form():
