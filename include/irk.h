@@ -152,12 +152,16 @@ void irk_problem_destroy(irk_problem *p);
 
 /* y = M x on one nodal vector: the consistent mass matrix M of eq:rkheat (Section 2),
  * Dirichlet rows and columns removed (device, n doubles each; x and y must not overlap).
- * Used for objectives such as J = 1/2 |u - u_*|_M^2. */
+ * Used for objectives such as J = 1/2 |u - u_*|_M^2. Staging: two padded planes owned by the
+ * problem, allocated by the first irk_apply_mass / irk_apply_stiffness call on it; calls on one
+ * problem that overlap in time (different streams, threads) race on them. Only enqueues work. */
 int irk_apply_mass(const irk_problem *p, const double *x, double *y, void *stream);
 
 /* y = K x: the stiffness matrix K of eq:rkheat (Section 2) with the problem's kappa,
- * Dirichlet rows and columns removed (device, n doubles each; no overlap). */
+ * Dirichlet rows and columns removed (device, n doubles each; no overlap). Staging as
+ * irk_apply_mass. Only enqueues work. */
 int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *stream);
+
 
 /* Stepper (Section 2 time stepping of eq:rkheat with the stage system eq:block_struct_AI or
  * eq:block_struct_IA and a Section 3 preconditioner): a tableau, a time step and solver

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,8 +68,12 @@ size_t storage_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 
 struct irk_problem {
   int N = 0;
+  int dev = 0;  // device current at creation
   Geom g{};
   double* kappa = nullptr;  // padded element layout, FP64
+  // staging of irk_apply_mass / irk_apply_stiffness: two padded planes, allocated by the first such call
+  mutable double* stage = nullptr;
+  mutable std::mutex stage_mu;
 };
 
 namespace {
@@ -1128,6 +1133,28 @@ int forward_step(irk_stepper* st, const double* Fp, SolveInfo& si, hipStream_t s
 
 // ------------------------------------------------------------------ binomial checkpointing
 
+// y = M x (op 0) or K x (op 1) on one compact nodal vector, through two padded staging planes at xp (the pack
+// kernel writes every value of the first plane, boundary ring and padding as zeros; the stencil writes the
+// interior of the second, the only part unpack reads), enqueued on s
+int apply_nodal(const irk_problem* p, int op, const double* x, double* y, double* xp, hipStream_t s) {
+  double* yp = xp + p->g.plane;
+  launch_pack(x, xp, p->g, 1, s);
+  if (op == 0)
+    launch_mass(xp, yp, p->g, s);
+  else
+    launch_stiff(xp, yp, p->kappa, p->g, s);
+  launch_unpack(yp, y, p->g, 1, s);
+  return check_launch();
+}
+
+// the problem's staging planes (allocated by the first call that needs them)
+int problem_stage(const irk_problem* p, double** out) {
+  std::lock_guard<std::mutex> lk(p->stage_mu);
+  if (!p->stage) CHK(dev_alloc((void**)&p->stage, 2 * p->g.plane * sizeof(double)));
+  *out = p->stage;
+  return IRK_OK;
+}
+
 int validate_stepper(const irk_stepper* st) {
   if (!st) return fail(IRK_EINVAL, "stepper is NULL");
   return IRK_OK;
@@ -1171,6 +1198,10 @@ int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stre
   irk_problem* p = new irk_problem();
   p->N = N;
   p->g = make_geom(N);
+  if (hipGetDevice(&p->dev) != hipSuccess) {
+    delete p;
+    return fail(IRK_EHIP, "hipGetDevice failed");
+  }
   const long kc = (long)N * p->g.pitch;
   int rc = dev_alloc((void**)&p->kappa, kc * sizeof(double));
   if (rc != IRK_OK) {
@@ -1208,41 +1239,24 @@ int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stre
 void irk_problem_destroy(irk_problem* p) {
   if (!p) return;
   dev_free(p->kappa);
+  dev_free(p->stage);
   delete p;
 }
 
 int irk_apply_mass(const irk_problem* p, const double* x, double* y, void* stream) {
   g_err.clear();
   if (!p || !x || !y) return fail(IRK_EINVAL, "NULL argument");
-  hipStream_t s = S(stream);
-  double *xp = nullptr, *yp = nullptr;
-  CHK(dev_alloc((void**)&xp, 2 * p->g.plane * sizeof(double)));
-  yp = xp + p->g.plane;
-  launch_pack(x, xp, p->g, 1, s);
-  hipError_t e = hipMemsetAsync(yp, 0, p->g.plane * sizeof(double), s);
-  launch_mass(xp, yp, p->g, s);
-  launch_unpack(yp, y, p->g, 1, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(xp);
-  if (e != hipSuccess) return fail(IRK_EHIP, hipGetErrorString(e));
-  return check_launch();
+  double* xp = nullptr;
+  CHK(problem_stage(p, &xp));
+  return apply_nodal(p, 0, x, y, xp, S(stream));
 }
 
 int irk_apply_stiffness(const irk_problem* p, const double* x, double* y, void* stream) {
   g_err.clear();
   if (!p || !x || !y) return fail(IRK_EINVAL, "NULL argument");
-  hipStream_t s = S(stream);
   double* xp = nullptr;
-  CHK(dev_alloc((void**)&xp, 2 * p->g.plane * sizeof(double)));
-  double* yp = xp + p->g.plane;
-  launch_pack(x, xp, p->g, 1, s);
-  hipError_t e = hipMemsetAsync(yp, 0, p->g.plane * sizeof(double), s);
-  launch_stiff(xp, yp, p->kappa, p->g, s);
-  launch_unpack(yp, y, p->g, 1, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(xp);
-  if (e != hipSuccess) return fail(IRK_EHIP, hipGetErrorString(e));
-  return check_launch();
+  CHK(problem_stage(p, &xp));
+  return apply_nodal(p, 1, x, y, xp, S(stream));
 }
 
 void irk_stepper_destroy(irk_stepper* st) {
