@@ -162,6 +162,16 @@ int irk_apply_mass(const irk_problem *p, const double *x, double *y, void *strea
  * irk_apply_mass. Only enqueues work. */
 int irk_apply_stiffness(const irk_problem *p, const double *x, double *y, void *stream);
 
+/* y = M x exactly as irk_apply_mass (same kernels, same result bits), for callers that cannot
+ * allocate device memory: code under HIP stream capture, serving loops, harnesses that forbid
+ * hipMalloc. It calls no allocating routine: its staging (two padded planes) is a static device
+ * array of 2 * 1025 * 1040 doubles (17.1 MB) that every GPU the library runs on holds until the
+ * process ends, so N <= 1024 (IRK_EINVAL beyond, with a message). The array's device address is
+ * looked up once per device, on the first call for a problem of that device, which must then be
+ * the current device (IRK_EINVAL otherwise). Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (different streams or threads) race and must be ordered by the
+ * caller. Only enqueues work (x, y: device, n doubles each, no overlap). */
+int irk_apply_mass_noalloc(const irk_problem *p, const double *x, double *y, void *stream);
 
 /* Stepper (Section 2 time stepping of eq:rkheat with the stage system eq:block_struct_AI or
  * eq:block_struct_IA and a Section 3 preconditioner): a tableau, a time step and solver

@@ -107,7 +107,7 @@ _lib = None
 
 SYMBOLS = [
     "irk_last_error", "irk_options_default", "irk_problem_create", "irk_problem_destroy", "irk_apply_mass",
-    "irk_apply_stiffness", "irk_stepper_create", "irk_stepper_destroy", "irk_stage_rhs", "irk_apply_stage_operator",
+    "irk_apply_stiffness", "irk_apply_mass_noalloc", "irk_stepper_create", "irk_stepper_destroy", "irk_stage_rhs", "irk_apply_stage_operator",
     "irk_apply_preconditioner", "irk_vcycle", "irk_solve_stages", "irk_advance", "irk_adjoint",
     "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_read",
 ]
@@ -131,6 +131,7 @@ def lib():
     L.irk_problem_destroy.argtypes = [vp]
     L.irk_apply_mass.argtypes = [vp, vp, vp, vp]
     L.irk_apply_stiffness.argtypes = [vp, vp, vp, vp]
+    L.irk_apply_mass_noalloc.argtypes = [vp, vp, vp, vp]
     L.irk_stepper_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(_Tableau), ctypes.c_double,
                                      ctypes.POINTER(Options), vp]
     L.irk_stepper_destroy.restype = None
@@ -220,6 +221,12 @@ class Problem:
     def apply_mass(self, x, stream=None):
         y = _torch().empty_like(x)
         _check(lib().irk_apply_mass(self._h, _dev_ptr(x, self.n, "x"), _dev_ptr(y), _stream(stream)))
+        return y
+
+    def apply_mass_noalloc(self, x, y, stream=None):
+        """y = M x into the caller's y without any device allocation by the library (N <= 1024)."""
+        _check(lib().irk_apply_mass_noalloc(self._h, _dev_ptr(x, self.n, "x"), _dev_ptr(y, self.n, "y"),
+                                            _stream(stream)))
         return y
 
     def apply_stiffness(self, x, stream=None):

@@ -1155,6 +1155,31 @@ int problem_stage(const irk_problem* p, double** out) {
   return IRK_OK;
 }
 
+// Staging of irk_apply_mass_noalloc: a static device array (two padded planes at N = kScratchMaxN), which every
+// GPU the library runs on holds until the process ends. In host code its name is only a stand-in: the device
+// address is looked up once per device (hipGetSymbolAddress, with that device current) and used from then on.
+constexpr int kScratchMaxN = 1024;
+constexpr long kScratchDoubles = 2L * (kScratchMaxN + 1) * ((kScratchMaxN + 1 + 15) / 16 * 16);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;
+
+int scratch_of_device(int dev, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev)
+      return fail(IRK_EINVAL, "the problem's device (" + std::to_string(dev) + ") must be current on the first call");
+    void* a = nullptr;
+    HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (double*)a;
+  }
+  *out = g_scratch_ptr[dev];
+  return IRK_OK;
+}
+
 int validate_stepper(const irk_stepper* st) {
   if (!st) return fail(IRK_EINVAL, "stepper is NULL");
   return IRK_OK;
@@ -1257,6 +1282,17 @@ int irk_apply_stiffness(const irk_problem* p, const double* x, double* y, void* 
   double* xp = nullptr;
   CHK(problem_stage(p, &xp));
   return apply_nodal(p, 1, x, y, xp, S(stream));
+}
+
+int irk_apply_mass_noalloc(const irk_problem* p, const double* x, double* y, void* stream) {
+  g_err.clear();
+  if (!p || !x || !y) return fail(IRK_EINVAL, "NULL argument");
+  if (2 * p->g.plane > kScratchDoubles)
+    return fail(IRK_EINVAL, "irk_apply_mass_noalloc supports N <= " + std::to_string(kScratchMaxN) + " (N = " +
+                                std::to_string(p->N) + "); use irk_apply_mass");
+  double* xp = nullptr;
+  CHK(scratch_of_device(p->dev, &xp));
+  return apply_nodal(p, 0, x, y, xp, S(stream));
 }
 
 void irk_stepper_destroy(irk_stepper* st) {
