@@ -256,15 +256,36 @@ int irk_stepper_mu(const irk_stepper *st, int stage, int level, double *mu);
  * `level` (0 = finest; 0 on the coarsest) of the forward (transpose = 0) or transposed system. */
 int irk_stepper_mmg_mu(const irk_stepper *st, int transpose, int level, double *mu, int *levels);
 
-/* Measurement hook. While enabled, every launch of kernel `family` on a full stage
- * block is bracketed by HIP events recorded on the stream it is launched on, and its
- * algorithmic bytes are accumulated; Krylov iterations are launched eagerly (not
- * replayed from graphs) meanwhile, with the same kernels and arithmetic.
- * family 0 = the streaming Gram-Schmidt pass (basis vectors read, w read, w written
- * when updated; 8 bytes per interior value). Enabling resets the counters. */
+/* Measurement hook: kernel families of a step, timed by irk_kernel_timer. */
+enum {
+  IRK_KFAM_GRAM_SCHMIDT = 0,   /* streaming Gram-Schmidt passes over the Krylov vectors (also norms, updates)  */
+  IRK_KFAM_OPERATOR = 1,       /* stage operator (and residual) applications                                   */
+  IRK_KFAM_MG_FINE = 2,        /* finest-level multigrid DOWN and UP kernels (single-stage and monolithic)    */
+  IRK_KFAM_MG_COARSE = 3,      /* multigrid DOWN and UP kernels on the coarser levels                          */
+  IRK_KFAM_COARSE_SOLVE = 4,   /* dense coarsest-level solves                                                  */
+  IRK_KFAM_REDUCE_FINISH = 5,  /* one-block finishing kernels of the reductions                                */
+  IRK_KFAM_OTHER = 6,          /* stage right-hand side, update, block-triangular coupling on one-level grids  */
+  IRK_KFAM_COUNT = 7,
+  IRK_KFAM_ALL = 100           /* every family above                                                           */
+};
+
+/* While enabled, every dispatch of kernel family `family` (or of all families) during the
+ * solver's time steps and stage solves carries HIP start/stop events attached to the dispatch
+ * itself (hipExtLaunchKernelGGL on the stream the kernel runs on), and its algorithmic bytes are
+ * accumulated: the streaming passes count each vector they read or write (8 bytes a value); the
+ * multigrid kernels count two figures, the per-pass model (every smoothing, residual and transfer
+ * pass streaming its vectors: per node 8.25 p for DOWN and for UP with p the bytes of a stored
+ * value, plus the diffusivity once per smoothing pass, plus 8 bytes per coupled FP64 stage
+ * plane) and the fused minimum (what the fused kernel reads and writes once); the coarsest solve
+ * counts its inverse and vectors. Krylov iterations are launched eagerly (not replayed from
+ * graphs) meanwhile, with the same kernels and arithmetic. Enabling resets the counters. */
 int irk_kernel_timer(irk_stepper *st, int family, int enable);
-/* Launches timed, their summed duration (ms) and their summed algorithmic bytes.
+/* For one family (or IRK_KFAM_ALL): dispatches timed, their summed duration (ms), and their
+ * summed algorithmic bytes (per-pass model and fused minimum; each pointer may be NULL).
  * Synchronises on the recorded events. */
+int irk_kernel_timer_family(irk_stepper *st, int family, int *launches, double *total_ms, double *bytes,
+                            double *bytes_min);
+/* The same over all timed families (per-pass model bytes). */
 int irk_kernel_timer_read(irk_stepper *st, int *launches, double *total_ms, double *bytes);
 
 #ifdef __cplusplus

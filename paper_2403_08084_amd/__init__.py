@@ -45,6 +45,9 @@ F64, F32, BF16 = 0, 1, 2
 ORTH_CGS2, ORTH_CGS_SELECTIVE, ORTH_DCGS2 = 0, 1, 2
 GUESS_ZERO, GUESS_PREV = 0, 1
 LOOKAHEAD_OFF, LOOKAHEAD_ADAPTIVE, LOOKAHEAD_ALWAYS = 0, 1, 2
+KFAM_GRAM_SCHMIDT, KFAM_OPERATOR, KFAM_MG_FINE, KFAM_MG_COARSE, KFAM_COARSE_SOLVE, KFAM_REDUCE_FINISH, KFAM_OTHER = range(7)
+KFAM_NAMES = ["gram_schmidt", "operator", "mg_fine", "mg_coarse", "coarse_solve", "reduce_finish", "other"]
+KFAM_ALL = 100
 
 _STATUS = {IRK_EINVAL: "EINVAL", IRK_ENOMEM: "ENOMEM", IRK_EHIP: "EHIP", IRK_ENOCONV: "ENOCONV",
            IRK_EBREAKDOWN: "EBREAKDOWN"}
@@ -109,7 +112,7 @@ SYMBOLS = [
     "irk_last_error", "irk_options_default", "irk_problem_create", "irk_problem_destroy", "irk_apply_mass",
     "irk_apply_stiffness", "irk_apply_mass_noalloc", "irk_stepper_create", "irk_stepper_destroy", "irk_stage_rhs", "irk_apply_stage_operator",
     "irk_apply_preconditioner", "irk_vcycle", "irk_solve_stages", "irk_advance", "irk_adjoint",
-    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_read",
+    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_family", "irk_kernel_timer_read",
 ]
 
 
@@ -150,6 +153,7 @@ def lib():
     L.irk_stepper_mmg_mu.argtypes = [vp, ip, ip, dp, ctypes.POINTER(ip)]
     L.irk_kernel_timer.argtypes = [vp, ip, ip]
     L.irk_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ip), dp, dp]
+    L.irk_kernel_timer_family.argtypes = [vp, ip, ctypes.POINTER(ip), dp, dp, dp]
     for name in SYMBOLS:
         if name not in ("irk_last_error", "irk_options_default", "irk_problem_destroy", "irk_stepper_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -293,16 +297,24 @@ class Stepper:
         return v.value
 
     def kernel_timer(self, family: int = 0, enable: bool = True):
-        """Enable/disable the HIP-event measurement hook for a kernel family (0 = Gram-Schmidt pass)."""
+        """Enable/disable the HIP-event measurement hook for a kernel family (KFAM_*, or KFAM_ALL)."""
         _check(lib().irk_kernel_timer(self._h, int(family), int(bool(enable))))
 
     def kernel_timer_read(self):
-        """(launches, total_ms, algorithmic_bytes) accumulated since the hook was enabled."""
+        """(launches, total_ms, algorithmic_bytes) accumulated over the timed families since enabling."""
         n = ctypes.c_int()
         ms = ctypes.c_double()
         by = ctypes.c_double()
         _check(lib().irk_kernel_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
         return n.value, ms.value, by.value
+
+    def kernel_timer_family(self, family: int):
+        """(launches, total_ms, bytes per-pass model, bytes fused minimum) of one family (or KFAM_ALL)."""
+        n = ctypes.c_int()
+        ms, by, bm = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().irk_kernel_timer_family(self._h, int(family), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                             ctypes.byref(bm)))
+        return n.value, ms.value, by.value, bm.value
 
     def stage_rhs(self, u, F=None, stream=None):
         f = _torch().empty(self.s * self.n, dtype=u.dtype, device=u.device)

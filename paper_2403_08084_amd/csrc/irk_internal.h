@@ -11,6 +11,7 @@
 // field uses N rows of the same pitch: element (ex, ey) at ey*pitch + ex.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -91,6 +92,24 @@ struct MMGCoef {
   double adj[kMMGMax * kMMGMax * kMMGMax];  // [k][q][r]
   double det[kMMGMax + 1];
 };
+
+// ---------------------------------------------------------------- measurement hook
+// Start/stop events that the next launch of a wrapper attaches to its dispatch (kernel start and end
+// timestamps); the runtime sets them just before calling the wrapper, whose first launch consumes them.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_ev;
+
+template <typename K, typename... A>
+inline void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
+  const LaunchEvents ev = g_launch_ev;
+  g_launch_ev = LaunchEvents{};
+  if (ev.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev.start, ev.stop, 0, args...);
+  else
+    kernel<<<grid, block, 0, st>>>(args...);
+}
 
 // ---------------------------------------------------------------- layout (k_stencil.hip)
 void launch_pack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st);

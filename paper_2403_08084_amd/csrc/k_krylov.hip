@@ -385,7 +385,7 @@ void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st, hipE
       hipExtLaunchKernelGGL(ortho_kernel<0, NORM>, dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, b, rw);
     else
       ortho_kernel<0, NORM><<<nb, NT, 0, st>>>(b, rw);
-    finish_kernel<0><<<1, NF, 0, st>>>(b, rw, nb);
+    launch_k(finish_kernel<0>, dim3(1), dim3(NF), st, b, rw, nb);
     return;
   }
   const int mode = (ax && dt) ? AXPY_DOTS : (ax ? AXPY : DOTS);
@@ -394,7 +394,7 @@ void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st, hipE
     hipExtLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a, rw);
   else
     hipLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, a, rw);
-  hipLaunchKernelGGL(T::fin(a.nv), dim3(1), dim3(NF), 0, st, a, rw, nb);
+  launch_k(T::fin(a.nv), dim3(1), dim3(NF), st, a, rw, nb);
 }
 
 int dcgs2_blocks(long len, const ReduceWork& rw) {
@@ -411,7 +411,7 @@ void launch_dcgs2_dots(const D2Args& a, const ReduceWork& rw, hipStream_t st, hi
     hipExtLaunchKernelGGL(T::dots(a.nv), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a, rw);
   else
     hipLaunchKernelGGL(T::dots(a.nv), dim3(nb), dim3(NT), 0, st, a, rw);
-  hipLaunchKernelGGL(T::fin(a.nv), dim3(1), dim3(NF2), 0, st, a, rw, nb);
+  launch_k(T::fin(a.nv), dim3(1), dim3(NF2), st, a, rw, nb);
 }
 
 void launch_dcgs2_update(const D2Args& a, const ReduceWork& rw, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {

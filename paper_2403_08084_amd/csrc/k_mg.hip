@@ -417,16 +417,13 @@ void down_shape(const TV* tt, const double* tscale, TS* xx, TS* cc, TC* to, cons
   constexpr int B = NW * WL, C = CP ? 1 : 0;
   switch (c.deg) {
     case 1:
-      mg_down_kernel<TV, TS, TC, 1, NW, RW, CP>
-          <<<level_grid<NW, RW, 2 + C>(g), B, 0, st>>>(tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      launch_k(mg_down_kernel<TV, TS, TC, 1, NW, RW, CP>, level_grid<NW, RW, 2 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
       break;
     case 2:
-      mg_down_kernel<TV, TS, TC, 2, NW, RW, CP>
-          <<<level_grid<NW, RW, 3 + C>(g), B, 0, st>>>(tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      launch_k(mg_down_kernel<TV, TS, TC, 2, NW, RW, CP>, level_grid<NW, RW, 3 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
       break;
     default:
-      mg_down_kernel<TV, TS, TC, 3, NW, RW, CP>
-          <<<level_grid<NW, RW, 4 + C>(g), B, 0, st>>>(tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      launch_k(mg_down_kernel<TV, TS, TC, 3, NW, RW, CP>, level_grid<NW, RW, 4 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
       break;
   }
 }
@@ -457,13 +454,13 @@ void up_shape(const TT* tt, const TS* xx, const TS* ee, TO* oo, const TC* kk, Ge
   constexpr int B = NW * WL;
   switch (c.deg) {
     case 1:
-      mg_up_kernel<TT, TS, TO, TC, 1, NW, RW><<<level_grid<NW, RW, 1>(g), B, 0, st>>>(tt, xx, ee, oo, kk, g, gc, c);
+      launch_k(mg_up_kernel<TT, TS, TO, TC, 1, NW, RW>, level_grid<NW, RW, 1>(g), B, st, tt, xx, ee, oo, kk, g, gc, c);
       break;
     case 2:
-      mg_up_kernel<TT, TS, TO, TC, 2, NW, RW><<<level_grid<NW, RW, 2>(g), B, 0, st>>>(tt, xx, ee, oo, kk, g, gc, c);
+      launch_k(mg_up_kernel<TT, TS, TO, TC, 2, NW, RW>, level_grid<NW, RW, 2>(g), B, st, tt, xx, ee, oo, kk, g, gc, c);
       break;
     default:
-      mg_up_kernel<TT, TS, TO, TC, 3, NW, RW><<<level_grid<NW, RW, 3>(g), B, 0, st>>>(tt, xx, ee, oo, kk, g, gc, c);
+      launch_k(mg_up_kernel<TT, TS, TO, TC, 3, NW, RW>, level_grid<NW, RW, 3>(g), B, st, tt, xx, ee, oo, kk, g, gc, c);
       break;
   }
 }
@@ -523,16 +520,16 @@ void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tsc
   const int n = (g.N - 1) * (g.N - 1);
   const dim3 grid((n + NTC / 64 - 1) / (NTC / 64));
   if (prec == 0) {
-    mg_coarse_kernel<double, double, double><<<grid, NTC, 0, st>>>((const double*)t, tscale, (double*)out,
+    launch_k(mg_coarse_kernel<double, double, double>, grid, NTC, st, (const double*)t, tscale, (double*)out,
                                                                  (const double*)Binv, g);
   } else if (io_is_f64) {
-    mg_coarse_kernel<double, double, float><<<grid, NTC, 0, st>>>((const double*)t, tscale, (double*)out,
+    launch_k(mg_coarse_kernel<double, double, float>, grid, NTC, st, (const double*)t, tscale, (double*)out,
                                                                 (const float*)Binv, g);
   } else if (prec == 1) {
-    mg_coarse_kernel<float, float, float><<<grid, NTC, 0, st>>>((const float*)t, tscale, (float*)out,
+    launch_k(mg_coarse_kernel<float, float, float>, grid, NTC, st, (const float*)t, tscale, (float*)out,
                                                               (const float*)Binv, g);
   } else {
-    mg_coarse_kernel<bf16, bf16, float><<<grid, NTC, 0, st>>>((const bf16*)t, tscale, (bf16*)out, (const float*)Binv,
+    launch_k(mg_coarse_kernel<bf16, bf16, float>, grid, NTC, st, (const bf16*)t, tscale, (bf16*)out, (const float*)Binv,
                                                             g);
   }
 }

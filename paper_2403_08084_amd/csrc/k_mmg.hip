@@ -547,7 +547,7 @@ void down_k(const void* t, const double* ts, void* x, void* tc, const void* kap,
             hipStream_t st) {
   constexpr int TX = MTile<TC, S, SMALL>::TX, TY = MTile<TC, S, SMALL>::TY;
   const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
-  mmg_down_kernel<TT, TS, TC, S, DEG, TX, TY><<<grid, NT, 0, st>>>((const TT*)t, ts, (TS*)x, (TS*)tc, (const TC*)kap,
+  launch_k(mmg_down_kernel<TT, TS, TC, S, DEG, TX, TY>, grid, NT, st, (const TT*)t, ts, (TS*)x, (TS*)tc, (const TC*)kap,
                                                                    g, gc, c);
 }
 
@@ -556,7 +556,7 @@ void up_k(const void* t, const double* ts, const void* x, const void* e, void* o
           const MMGCoef& c, hipStream_t st) {
   constexpr int TX = MTile<TC, S, SMALL>::TX, TY = MTile<TC, S, SMALL>::TY;
   const dim3 grid(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
-  mmg_up_kernel<TT, TS, TO, TC, S, DEG, TX, TY><<<grid, NT, 0, st>>>((const TT*)t, ts, (const TS*)x, (const TS*)e,
+  launch_k(mmg_up_kernel<TT, TS, TO, TC, S, DEG, TX, TY>, grid, NT, st, (const TT*)t, ts, (const TS*)x, (const TS*)e,
                                                                      (TO*)out, (const TC*)kap, g, gc, c);
 }
 
@@ -653,20 +653,20 @@ void launch_mmg_coarse(int prec, bool t_f64, bool out_f64, const void* t, const 
   const int n = s * (g.N - 1) * (g.N - 1);
   const dim3 grid((n + 3) / 4), blk(256);
   if (prec == 0) {
-    mmg_coarse_kernel<double, double, double><<<grid, blk, 0, st>>>((const double*)t, tscale, (double*)out,
+    launch_k(mmg_coarse_kernel<double, double, double>, grid, blk, st, (const double*)t, tscale, (double*)out,
                                                                      (const double*)Cinv, g, s);
   } else if (prec == 1) {
     const float* C = (const float*)Cinv;
-    if (t_f64 && out_f64) mmg_coarse_kernel<double, double, float><<<grid, blk, 0, st>>>((const double*)t, tscale, (double*)out, C, g, s);
-    else if (t_f64) mmg_coarse_kernel<double, float, float><<<grid, blk, 0, st>>>((const double*)t, tscale, (float*)out, C, g, s);
-    else if (out_f64) mmg_coarse_kernel<float, double, float><<<grid, blk, 0, st>>>((const float*)t, tscale, (double*)out, C, g, s);
-    else mmg_coarse_kernel<float, float, float><<<grid, blk, 0, st>>>((const float*)t, tscale, (float*)out, C, g, s);
+    if (t_f64 && out_f64) launch_k(mmg_coarse_kernel<double, double, float>, grid, blk, st, (const double*)t, tscale, (double*)out, C, g, s);
+    else if (t_f64) launch_k(mmg_coarse_kernel<double, float, float>, grid, blk, st, (const double*)t, tscale, (float*)out, C, g, s);
+    else if (out_f64) launch_k(mmg_coarse_kernel<float, double, float>, grid, blk, st, (const float*)t, tscale, (double*)out, C, g, s);
+    else launch_k(mmg_coarse_kernel<float, float, float>, grid, blk, st, (const float*)t, tscale, (float*)out, C, g, s);
   } else {
     const float* C = (const float*)Cinv;
-    if (t_f64 && out_f64) mmg_coarse_kernel<double, double, float><<<grid, blk, 0, st>>>((const double*)t, tscale, (double*)out, C, g, s);
-    else if (t_f64) mmg_coarse_kernel<double, bf16, float><<<grid, blk, 0, st>>>((const double*)t, tscale, (bf16*)out, C, g, s);
-    else if (out_f64) mmg_coarse_kernel<bf16, double, float><<<grid, blk, 0, st>>>((const bf16*)t, tscale, (double*)out, C, g, s);
-    else mmg_coarse_kernel<bf16, bf16, float><<<grid, blk, 0, st>>>((const bf16*)t, tscale, (bf16*)out, C, g, s);
+    if (t_f64 && out_f64) launch_k(mmg_coarse_kernel<double, double, float>, grid, blk, st, (const double*)t, tscale, (double*)out, C, g, s);
+    else if (t_f64) launch_k(mmg_coarse_kernel<double, bf16, float>, grid, blk, st, (const double*)t, tscale, (bf16*)out, C, g, s);
+    else if (out_f64) launch_k(mmg_coarse_kernel<bf16, double, float>, grid, blk, st, (const bf16*)t, tscale, (double*)out, C, g, s);
+    else launch_k(mmg_coarse_kernel<bf16, bf16, float>, grid, blk, st, (const bf16*)t, tscale, (bf16*)out, C, g, s);
   }
 }
 
@@ -674,10 +674,10 @@ void launch_mmg_apply(const double* x, double* out, const double* kap, Geom g, c
                       hipStream_t st) {
   const dim3 grid = mmg_grid(g), blk(MX, MY);
   switch (c.s) {
-    case 1: mmg_apply_kernel<1><<<grid, blk, 0, st>>>(x, out, kap, g, c, mode); break;
-    case 2: mmg_apply_kernel<2><<<grid, blk, 0, st>>>(x, out, kap, g, c, mode); break;
-    case 3: mmg_apply_kernel<3><<<grid, blk, 0, st>>>(x, out, kap, g, c, mode); break;
-    default: mmg_apply_kernel<4><<<grid, blk, 0, st>>>(x, out, kap, g, c, mode); break;
+    case 1: launch_k(mmg_apply_kernel<1>, grid, blk, st, x, out, kap, g, c, mode); break;
+    case 2: launch_k(mmg_apply_kernel<2>, grid, blk, st, x, out, kap, g, c, mode); break;
+    case 3: launch_k(mmg_apply_kernel<3>, grid, blk, st, x, out, kap, g, c, mode); break;
+    default: launch_k(mmg_apply_kernel<4>, grid, blk, st, x, out, kap, g, c, mode); break;
   }
 }
 

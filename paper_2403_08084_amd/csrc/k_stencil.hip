@@ -387,25 +387,25 @@ int flat_blocks(long n) {
 }  // namespace
 
 void launch_pack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st) {
-  pack_kernel<<<dim3(flat_blocks(g.plane), nplanes), 256, 0, st>>>(src, dst, g);
+  launch_k(pack_kernel, dim3(flat_blocks(g.plane), nplanes), 256, st, src, dst, g);
 }
 void launch_unpack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st) {
-  unpack_kernel<<<dim3(flat_blocks((long)(g.N - 1) * (g.N - 1)), nplanes), 256, 0, st>>>(src, dst, g);
+  launch_k(unpack_kernel, dim3(flat_blocks((long)(g.N - 1) * (g.N - 1)), nplanes), 256, st, src, dst, g);
 }
 void launch_pack_elem(const double* src, double* dst, Geom g, hipStream_t st) {
-  pack_elem_kernel<<<flat_blocks((long)g.N * g.pitch), 256, 0, st>>>(src, dst, g);
+  launch_k(pack_elem_kernel, flat_blocks((long)g.N * g.pitch), 256, st, src, dst, g);
 }
 void launch_unpack_elem(const double* src, double* dst, Geom g, hipStream_t st) {
-  unpack_elem_kernel<<<flat_blocks((long)g.N * g.N), 256, 0, st>>>(src, dst, g);
+  launch_k(unpack_elem_kernel, flat_blocks((long)g.N * g.N), 256, st, src, dst, g);
 }
 void launch_check_kappa(const double* kappa, int count, int* bad, hipStream_t st) {
-  check_kappa_kernel<<<flat_blocks(count), 256, 0, st>>>(kappa, count, bad);
+  launch_k(check_kappa_kernel, flat_blocks(count), 256, st, kappa, count, bad);
 }
 void launch_cast_f32(const double* src, float* dst, long count, hipStream_t st) {
-  cast_f32_kernel<<<flat_blocks(count), 256, 0, st>>>(src, dst, count);
+  launch_k(cast_f32_kernel, flat_blocks(count), 256, st, src, dst, count);
 }
 void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, hipStream_t st) {
-  coarsen_kappa_kernel<<<flat_blocks((long)gc.N * gc.pitch), 256, 0, st>>>(fine, coarse, gf, gc);
+  launch_k(coarsen_kappa_kernel, flat_blocks((long)gc.N * gc.pitch), 256, st, fine, coarse, gf, gc);
 }
 
 template <bool IA>
@@ -414,14 +414,14 @@ void stage_operator_t(const double* x, double* y, const double* f, const double*
   const int ntx = (g.N - 1 + BX - 1) / BX, nty = (g.N - 1 + BY * RB - 1) / (BY * RB);
   const dim3 grid(ntx * nty), blk(BX, BY);
   switch (s) {
-    case 1: stage_operator_kernel<1, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 2: stage_operator_kernel<2, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 3: stage_operator_kernel<3, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 4: stage_operator_kernel<4, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 5: stage_operator_kernel<5, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 6: stage_operator_kernel<6, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    case 7: stage_operator_kernel<7, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
-    default: stage_operator_kernel<8, IA><<<grid, blk, 0, st>>>(x, y, f, kappa, g, a, dt); break;
+    case 1: launch_k(stage_operator_kernel<1, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 2: launch_k(stage_operator_kernel<2, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 3: launch_k(stage_operator_kernel<3, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 4: launch_k(stage_operator_kernel<4, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 5: launch_k(stage_operator_kernel<5, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 6: launch_k(stage_operator_kernel<6, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 7: launch_k(stage_operator_kernel<7, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    default: launch_k(stage_operator_kernel<8, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
   }
 }
 
@@ -433,41 +433,41 @@ void launch_stage_operator(const double* x, double* y, const double* f, const do
     stage_operator_t<false>(x, y, f, kappa, g, s, a, dt, st);
 }
 void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st) {
-  stage_rhs_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(u, F, f, kappa, g, s);
+  launch_k(stage_rhs_kernel, stencil_grid(g), dim3(BX, BY), st, u, F, f, kappa, g, s);
 }
 void launch_mass(const double* x, double* y, Geom g, hipStream_t st) {
-  mass_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, y, g);
+  launch_k(mass_kernel, stencil_grid(g), dim3(BX, BY), st, x, y, g);
 }
 void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st) {
-  stiff_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, y, kappa, g);
+  launch_k(stiff_kernel, stencil_grid(g), dim3(BX, BY), st, x, y, kappa, g);
 }
 void launch_gs_couple(const double* v, const double* vscale, const double* z, int nz, const Coefs& row, double dt,
                       const double* kappa, double* t, Geom g, hipStream_t st, int mass, double vmul) {
-  gs_couple_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(v, vscale, z, nz, row, dt, kappa, t, g, mass, vmul);
+  launch_k(gs_couple_kernel, stencil_grid(g), dim3(BX, BY), st, v, vscale, z, nz, row, dt, kappa, t, g, mass, vmul);
 }
 void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st) {
-  update_kernel<<<flat_blocks(g.plane), 256, 0, st>>>(u, k, s, b, dt, g.plane);
+  launch_k(update_kernel, flat_blocks(g.plane), 256, st, u, k, s, b, dt, g.plane);
 }
 void launch_adjoint_rhs(const double* lam, double* f, int s, const Coefs& b, double dt, Geom g, hipStream_t st) {
-  adjoint_rhs_kernel<<<flat_blocks(g.plane), 256, 0, st>>>(lam, f, s, b, dt, g.plane);
+  launch_k(adjoint_rhs_kernel, flat_blocks(g.plane), 256, st, lam, f, s, b, dt, g.plane);
 }
 void launch_lambda_update(double* lam, const double* nu, int s, const double* kappa, Geom g, hipStream_t st) {
-  lambda_update_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(lam, nu, s, kappa, g);
+  launch_k(lambda_update_kernel, stencil_grid(g), dim3(BX, BY), st, lam, nu, s, kappa, g);
 }
 void launch_kappa_grad(double* grad, const double* u, const double* k, const double* nu, const double* kappa, Geom g,
                        int s, const Coefs& a, double dt, hipStream_t st) {
   const dim3 blk(64, 4), grid((g.N + 63) / 64, (g.N + 3) / 4);
-  kappa_grad_kernel<<<grid, blk, 0, st>>>(grad, u, k, nu, kappa, g, s, a, dt);
+  launch_k(kappa_grad_kernel, grid, blk, st, grad, u, k, nu, kappa, g, s, a, dt);
 }
 void launch_level_apply(const double* x, double* y, const double* kappa, Geom g, double alpha, int mode,
                         hipStream_t st) {
-  level_apply_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, y, kappa, g, alpha, mode);
+  launch_k(level_apply_kernel, stencil_grid(g), dim3(BX, BY), st, x, y, kappa, g, alpha, mode);
 }
 void launch_start_vector(double* x, Geom g, int level, hipStream_t st, uint64_t offset) {
-  start_vector_kernel<<<stencil_grid(g), dim3(BX, BY), 0, st>>>(x, g, level, offset);
+  launch_k(start_vector_kernel, stencil_grid(g), dim3(BX, BY), st, x, g, level, offset);
 }
 void launch_scale(double* x, long n, const double* nrm2, hipStream_t st) {
-  scale_kernel<<<flat_blocks(n), 256, 0, st>>>(x, n, nrm2);
+  launch_k(scale_kernel, flat_blocks(n), 256, st, x, n, nrm2);
 }
 
 }  // namespace irk

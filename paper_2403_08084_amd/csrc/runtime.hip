@@ -17,6 +17,8 @@
 
 using namespace irk;
 
+thread_local irk::LaunchEvents irk::g_launch_ev;
+
 namespace {
 
 thread_local std::string g_err;
@@ -144,12 +146,16 @@ struct irk_stepper {
   hipEvent_t step_ev[2] = {nullptr, nullptr};  // recorded on the solver's stream after step j
   hipEvent_t norm_ev = nullptr;                // behind the initial norms of a solve
   int last_its[2 + kMaxStages] = {};           // iterations of the last solve per system (as graphs[])
-  // measurement hook: events around every launch of one kernel family (eager launches only)
-  int timer_family = -1;
+  // measurement hook: start/stop events on every dispatch of the timed kernel families (eager launches only),
+  // with each dispatch's family and the algorithmic bytes it moves (two counts: the per-pass model, and the
+  // minimum of the fused kernels)
+  int timer_family = -1;                  // -1 off, a family, or IRK_KFAM_ALL
   std::vector<hipEvent_t> timer_ev;       // pairs (start, end)
+  std::vector<int> timer_tag;             // family of each pair
   size_t timer_used = 0;
-  double timer_bytes = 0;
-  int timer_launches = 0;
+  double timer_bytes[IRK_KFAM_COUNT] = {};
+  double timer_bytes_min[IRK_KFAM_COUNT] = {};
+  int timer_launches[IRK_KFAM_COUNT] = {};
   // one graph per Arnoldi index j, per system: [0] coupled forward, [1] coupled transposed,
   // [2 + i] the single-stage system of DIRK stage i
   std::vector<hipGraphExec_t> graphs[2 + kMaxStages];
@@ -202,10 +208,11 @@ Coefs b_of(const irk_stepper* st) {
 
 // ------------------------------------------------------------------ reductions
 
-// Next (start, end) event pair of the measurement hook, or nulls when the family is not timed.
-int timer_pair(irk_stepper* st, int family, hipEvent_t* e0, hipEvent_t* e1) {
+// Next (start, end) event pair of the measurement hook for one dispatch of `family` moving `bytes` (per-pass
+// model) and `bytes_min` (fused minimum) algorithmic bytes, or nulls when the family is not timed.
+int timer_pair(irk_stepper* st, int family, double bytes, double bytes_min, hipEvent_t* e0, hipEvent_t* e1) {
   *e0 = *e1 = nullptr;
-  if (st->timer_family != family) return IRK_OK;
+  if (st->timer_family != family && st->timer_family != IRK_KFAM_ALL) return IRK_OK;
   if (st->timer_used + 2 > st->timer_ev.size()) {
     for (int q = 0; q < 256; ++q) {
       hipEvent_t e;
@@ -213,11 +220,72 @@ int timer_pair(irk_stepper* st, int family, hipEvent_t* e0, hipEvent_t* e1) {
       st->timer_ev.push_back(e);
     }
   }
+  if (st->timer_tag.size() < st->timer_ev.size() / 2) st->timer_tag.resize(st->timer_ev.size() / 2);
+  st->timer_tag[st->timer_used / 2] = family;
   *e0 = st->timer_ev[st->timer_used++];
   *e1 = st->timer_ev[st->timer_used++];
-  st->timer_launches++;
+  st->timer_launches[family]++;
+  st->timer_bytes[family] += bytes;
+  st->timer_bytes_min[family] += bytes_min;
   return IRK_OK;
 }
+
+// the same, handed to the next launch of a wrapper (launch_k)
+int timer_arm(irk_stepper* st, int family, double bytes, double bytes_min) {
+  hipEvent_t e0, e1;
+  CHK(timer_pair(st, family, bytes, bytes_min, &e0, &e1));
+  g_launch_ev.start = e0;
+  g_launch_ev.stop = e1;
+  return IRK_OK;
+}
+
+// interior nodes of a level
+double nodes(const Geom& g) { return (double)(g.N - 1) * (double)(g.N - 1); }
+
+// Algorithmic bytes of the multigrid kernels, as (per-pass model, fused minimum). The per-pass model counts what
+// the V-cycle moves when every smoothing, residual and transfer pass streams its vectors (per node: 5p for
+// Chebyshev(2) pre-smoothing, 3p + p/4 for the residual and its restriction, 2p + p/4 for the prolongation and
+// correction, 6p for the post-smoothing, with p the bytes of a stored value, plus the element diffusivity once
+// per smoother pass); the fused minimum counts what the fused level kernels read and write once.
+struct Bytes {
+  double model, min;
+};
+double compute_bytes(const irk_stepper* st) { return st->prec == 0 ? 8.0 : 4.0; }
+
+// single-stage DOWN on level l (nz coupled FP64 stage planes read at the finest level)
+Bytes mg_down_bytes(const irk_stepper* st, int l, int nz) {
+  const double n = nodes(st->lv[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st);
+  const double tin = l == 0 ? 8.0 : p, tout = l == 0 ? c : 0.0;
+  return {n * (8.25 * p + 2 * c + 8.0 * nz), n * (tin + c + p + 0.25 * p + tout + 8.0 * nz)};
+}
+
+Bytes mg_up_bytes(const irk_stepper* st, int l) {
+  const double n = nodes(st->lv[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st);
+  const double tin = l == 0 ? c : p, out = l == 0 ? 8.0 : p;
+  return {n * (8.25 * p + 2 * c), n * (tin + p + 0.25 * p + c + out)};
+}
+
+// dense coarsest solve on nv unknowns: the inverse once, the right-hand side and the result
+Bytes coarse_bytes(const irk_stepper* st, double nv, bool io64) {
+  const double c = compute_bytes(st), io = io64 ? 16.0 : 2.0 * (double)storage_bytes(st->prec);
+  const double b = nv * nv * c + nv * io;
+  return {b, b};
+}
+
+// monolithic DOWN / UP on level l (s planes)
+Bytes mmg_down_bytes(const irk_stepper* st, int l) {
+  const double n = nodes(st->ml[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st), s = st->s;
+  const double tin = l == 0 ? 8.0 : p;
+  return {n * (s * 8.25 * p + 2 * c), n * (s * tin + c + s * p + s * 0.25 * p)};
+}
+
+Bytes mmg_up_bytes(const irk_stepper* st, int l) {
+  const double n = nodes(st->ml[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st), s = st->s;
+  const double io = l == 0 ? 8.0 : p;
+  return {n * (s * 8.25 * p + 2 * c), n * (s * io + s * p + s * 0.25 * p + c + s * io)};
+}
+
+int arm(irk_stepper* st, int family, const Bytes& b) { return timer_arm(st, family, b.model, b.min); }
 
 // Algorithmic bytes of one streaming Gram-Schmidt pass over s*n interior values:
 // the basis vectors it reads, w read, and w written when it updates w.
@@ -239,9 +307,10 @@ int ortho(irk_stepper* st, const OrthoArgs& a, hipStream_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // only passes over the Krylov vectors are timed (not the setup's per-level norms); with DCGS2 the timed
   // family is its reduction and update passes alone
-  if (a.len == sys_len(st) && st->opt.orth != IRK_ORTH_DCGS2) {
-    CHK(timer_pair(st, 0, &e0, &e1));
-    if (e0) st->timer_bytes += ortho_bytes(st, a);
+  if (a.len == sys_len(st)) {
+    const double b = ortho_bytes(st, a);
+    CHK(timer_pair(st, IRK_KFAM_GRAM_SCHMIDT, b, b, &e0, &e1));
+    CHK(timer_arm(st, IRK_KFAM_REDUCE_FINISH, 0, 0));
   }
   launch_ortho(a, st->rw, s, e0, e1);
   return check_launch();
@@ -591,17 +660,24 @@ int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, double* o
   const int pr = st->prec, ns = st->s;
   const MMGCoef* cf = st->mcoef[trans ? 1 : 0].data();
   const void* cinv = st->mcinv[trans ? 1 : 0];
+  const double nc = (double)ns * nodes(ml[L - 1].g);
   if (L == 1) {
+    CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nc, true)));
     launch_mmg_coarse(pr, true, true, t, tscale, out, cinv, ml[0].g, ns, s);
     return check_launch();
   }
-  for (int l = 0; l < L - 1; ++l)
+  for (int l = 0; l < L - 1; ++l) {
+    CHK(arm(st, l == 0 ? IRK_KFAM_MG_FINE : IRK_KFAM_MG_COARSE, mmg_down_bytes(st, l)));
     launch_mmg_down(pr, l == 0, l == 0 ? (const void*)t : ml[l].t, l == 0 ? tscale : nullptr, ml[l].x, ml[l + 1].t,
                     ml[l].kapc, ml[l].g, ml[l + 1].g, cf[l], s);
+  }
+  CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nc, false)));
   launch_mmg_coarse(pr, false, false, ml[L - 1].t, nullptr, ml[L - 1].e, cinv, ml[L - 1].g, ns, s);
-  for (int l = L - 2; l >= 0; --l)
+  for (int l = L - 2; l >= 0; --l) {
+    CHK(arm(st, l == 0 ? IRK_KFAM_MG_FINE : IRK_KFAM_MG_COARSE, mmg_up_bytes(st, l)));
     launch_mmg_up(pr, l == 0, l == 0 ? (const void*)t : ml[l].t, l == 0 ? tscale : nullptr, ml[l].x, ml[l + 1].e,
                   l == 0 ? (void*)out : ml[l].e, ml[l].kapc, ml[l].g, ml[l + 1].g, cf[l], s);
+  }
   return check_launch();
 }
 
@@ -616,18 +692,26 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
   const MGCoef* cf = &st->coef[(size_t)stage * L];
   const int pr = st->prec;
   if (L == 1) {
+    CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nodes(st->lv[0].g), true)));
     launch_mg_coarse(pr, true, t, tscale, out, st->binv[stage], st->lv[0].g, s);
     return check_launch();
   }
   std::vector<Level>& lv = st->lv;
   // the finest DOWN stores the right-hand side it smoothed (scaled, with the stage coupling) for the finest UP
+  CHK(arm(st, IRK_KFAM_MG_FINE, mg_down_bytes(st, 0, cp.nz)));
   launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].tp, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
-  for (int l = 1; l < L - 1; ++l)
+  for (int l = 1; l < L - 1; ++l) {
+    CHK(arm(st, IRK_KFAM_MG_COARSE, mg_down_bytes(st, l, 0)));
     launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, nullptr, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l],
                    none, s);
+  }
+  CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nodes(lv[L - 1].g), false)));
   launch_mg_coarse(pr, false, lv[L - 1].t, nullptr, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
-  for (int l = L - 2; l >= 1; --l)
+  for (int l = L - 2; l >= 1; --l) {
+    CHK(arm(st, IRK_KFAM_MG_COARSE, mg_up_bytes(st, l)));
     launch_mg_up(pr, false, lv[l].t, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
+  }
+  CHK(arm(st, IRK_KFAM_MG_FINE, mg_up_bytes(st, 0)));
   launch_mg_up(pr, true, lv[0].tp, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
   return check_launch();
 }
@@ -674,6 +758,8 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
         Coefs r{};
         for (int q = 0; q < nc; ++q) r.a[q] = row[q];
         double* t = st->tmp2;
+        const double gb = nodes(st->g) * (24.0 + 8.0 * nc);
+        CHK(timer_arm(st, IRK_KFAM_OTHER, gb, gb));
         launch_gs_couple(vi, vscale, z + j0 * plane, nc, r, st->ia ? 1.0 : st->dt, st->prob->kappa, t, st->g, s,
                          st->ia ? 1 : 0, vmul);
         CHK(vcycle(st, i, t, nullptr, zi, s));
@@ -686,6 +772,9 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
 }
 
 int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s) {
+  const int ns = st->sys >= 0 ? 1 : st->s;
+  const double ob = nodes(st->g) * (16.0 * ns + 8.0 + (f ? 8.0 * ns : 0.0));
+  CHK(timer_arm(st, IRK_KFAM_OPERATOR, ob, ob));
   if (st->sys >= 0) {
     // one DIRK stage: M + dt a_ii K (symmetric)
     Coefs a{};
@@ -716,11 +805,11 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
     CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
     D2Args d{st->V, n, j, Vj, Vn, n, dcgs2_dev(st, j & 1), st->hmir_dev + (long)(j & 1) * kDcgs2Res};
     hipEvent_t e0, e1, e2, e3;
-    CHK(timer_pair(st, 0, &e0, &e1));
-    if (e0) st->timer_bytes += dcgs2_bytes(st, j, n, false);
+    const double b0 = dcgs2_bytes(st, j, n, false), b1 = dcgs2_bytes(st, j, n, true);
+    CHK(timer_pair(st, IRK_KFAM_GRAM_SCHMIDT, b0, b0, &e0, &e1));
+    CHK(timer_arm(st, IRK_KFAM_REDUCE_FINISH, 0, 0));
     launch_dcgs2_dots(d, st->rw, s, e0, e1);
-    CHK(timer_pair(st, 0, &e2, &e3));
-    if (e2) st->timer_bytes += dcgs2_bytes(st, j, n, true);
+    CHK(timer_pair(st, IRK_KFAM_GRAM_SCHMIDT, b1, b1, &e2, &e3));
     launch_dcgs2_update(d, st->rw, s, e2, e3);
     return check_launch();
   }
@@ -1123,10 +1212,13 @@ void init_stats(irk_stats* stats) {
 
 // one forward step on st->u (padded); stage derivatives left in st->k
 int forward_step(irk_stepper* st, const double* Fp, SolveInfo& si, hipStream_t s) {
+  const double n = nodes(st->g), rb = n * (16.0 + (Fp ? 8.0 : 0.0) + 8.0 * st->s), ub = n * (8.0 * st->s + 16.0);
+  CHK(timer_arm(st, IRK_KFAM_OTHER, rb, rb));
   launch_stage_rhs(st->u, Fp, st->f, st->prob->kappa, st->g, st->s, s);
   const bool guess = st->opt.initial_guess == IRK_GUESS_PREV && st->have_prev;
   CHK(stage_solve(st, st->f, false, guess, si, s));
   st->have_prev = true;
+  CHK(timer_arm(st, IRK_KFAM_OTHER, ub, ub));
   launch_update(st->u, st->k, st->s, b_of(st), st->dt, st->g, s);
   return check_launch();
 }
@@ -1774,28 +1866,47 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
 int irk_kernel_timer(irk_stepper* st, int family, int enable) {
   g_err.clear();
   CHK(validate_stepper(st));
-  if (family != 0) return fail(IRK_EINVAL, "unknown kernel family (0 = Gram-Schmidt pass)");
+  if (!(family >= 0 && family < IRK_KFAM_COUNT) && family != IRK_KFAM_ALL)
+    return fail(IRK_EINVAL, "unknown kernel family " + std::to_string(family));
   st->timer_family = enable ? family : -1;
   st->timer_used = 0;
-  st->timer_bytes = 0;
-  st->timer_launches = 0;
+  for (int f = 0; f < IRK_KFAM_COUNT; ++f) {
+    st->timer_bytes[f] = st->timer_bytes_min[f] = 0;
+    st->timer_launches[f] = 0;
+  }
   return IRK_OK;
 }
 
-int irk_kernel_timer_read(irk_stepper* st, int* launches, double* total_ms, double* bytes) {
+int irk_kernel_timer_family(irk_stepper* st, int family, int* launches, double* total_ms, double* bytes,
+                            double* bytes_min) {
   g_err.clear();
   CHK(validate_stepper(st));
-  double ms = 0;
+  if (!(family >= 0 && family < IRK_KFAM_COUNT) && family != IRK_KFAM_ALL)
+    return fail(IRK_EINVAL, "unknown kernel family " + std::to_string(family));
+  double ms = 0, by = 0, bymin = 0;
+  int n = 0;
   for (size_t q = 0; q + 1 < st->timer_used; q += 2) {
+    if (family != IRK_KFAM_ALL && st->timer_tag[q / 2] != family) continue;
     HIPCHK(hipEventSynchronize(st->timer_ev[q + 1]));
     float f = 0;
     HIPCHK(hipEventElapsedTime(&f, st->timer_ev[q], st->timer_ev[q + 1]));
     ms += f;
   }
-  if (launches) *launches = st->timer_launches;
+  for (int f = 0; f < IRK_KFAM_COUNT; ++f)
+    if (family == IRK_KFAM_ALL || family == f) {
+      by += st->timer_bytes[f];
+      bymin += st->timer_bytes_min[f];
+      n += st->timer_launches[f];
+    }
+  if (launches) *launches = n;
   if (total_ms) *total_ms = ms;
-  if (bytes) *bytes = st->timer_bytes;
+  if (bytes) *bytes = by;
+  if (bytes_min) *bytes_min = bymin;
   return IRK_OK;
+}
+
+int irk_kernel_timer_read(irk_stepper* st, int* launches, double* total_ms, double* bytes) {
+  return irk_kernel_timer_family(st, IRK_KFAM_ALL, launches, total_ms, bytes, nullptr);
 }
 
 }  // extern "C"
