@@ -177,6 +177,19 @@ void launch_mg_up(int prec, bool finest, const void* t, const void* x, const voi
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
                       hipStream_t st);
 
+// The three levels A, B = A/2, C = B/2 above the coarsest level D in one launch each way. Index 0..3 = A..D.
+// DOWN3 reads t[0] and writes x[0..2], t[1..3]; UP3 reads e[3], t[0..2], x[0..2] and writes e[0].
+struct ThreeLevels {
+  Geom g[4];
+  MGCoef c[3];
+  void* t[4];
+  void* x[3];
+  void* e[4];
+  const void* kap[3];
+};
+void launch_mg_down3(int prec, const ThreeLevels& z, hipStream_t st);
+void launch_mg_up3(int prec, const ThreeLevels& z, hipStream_t st);
+
 // ---------------------------------------------------------------- monolithic multigrid (k_mmg.hip)
 // prec as above; t_f64 / io_f64: t (and out) is an FP64 Krylov vector (s planes) instead of level storage.
 // DOWN: Chebyshev pre-smoothing from zero of Acal x = ts t, writes x and the restricted residual tc.

@@ -360,6 +360,464 @@ __global__ __launch_bounds__(NW* WL) void mg_up_kernel(const TT* __restrict__ t,
   }
 }
 
+// ---------------------------------------------------------------- three levels in one launch
+// The levels above the coarsest, A, B = A/2 and C = B/2 (256², 128², 64² over the 32² coarsest solve of a 1024²
+// grid), are short chains of dependent phases whose cost is mostly the launch and the round trips through global
+// memory. DOWN3 does their three DOWN steps in one launch: it smooths A on a 64-column region in column segments (as
+// mg_down_kernel), restricts the residual into an LDS region of B, smooths that, restricts into an LDS region of C,
+// smooths that and restricts C's residual to D. UP3 does the three UP steps from D's correction to A. Each block's
+// regions are deep enough that it needs nothing from its neighbours: the tiles nest (a C tile of CT nodes, a B tile
+// of 2CT, an A tile of 4CT for DOWN3), and the halo rings of every level are recomputed by the neighbouring blocks.
+// The two lower levels are stored flat in LDS (W x W nodes, row stride W; element tile (W+1) x (W+1) from one
+// element below-left of the region), one node per thread and loop step.
+
+// B x at flat node (li, lj) (and the diagonal D)
+template <typename TC, int W>
+__device__ __forceinline__ TC flat_bx(const TC* X, const TC* K, int li, int lj, TC m, TC alpha, TC& D) {
+  const int p = lj * W + li, q = lj * (W + 1) + li;
+  const TC kSW = K[q], kSE = K[q + 1], kNW = K[q + W + 1], kNE = K[q + W + 2];
+  const TC xc = X[p], xE = X[p + 1], xW = X[p - 1], xN = X[p + W], xS = X[p - W];
+  const TC xNE = X[p + W + 1], xNW = X[p + W - 1], xSE = X[p - W + 1], xSW = X[p - W - 1];
+  const TC ks = kSW + kSE + kNW + kNE;
+  const TC Kx = (TC)(2.0 / 3.0) * ks * xc -
+                (TC)(1.0 / 6.0) * ((kNE + kSE) * xE + (kNW + kSW) * xW + (kNE + kNW) * xN + (kSE + kSW) * xS) -
+                (TC)(1.0 / 3.0) * (kNE * xNE + kNW * xNW + kSE * xSE + kSW * xSW);
+  const TC Mx = m * ((TC)16 * xc + (TC)4 * (xE + xW + xN + xS) + (xNE + xNW + xSE + xSW));
+  D = (TC)16 * m + alpha * (TC)(2.0 / 3.0) * ks;
+  return Mx + alpha * Kx;
+}
+
+// element tile of a flat region at level origin (ox, oy): (W+1) x (HM+1) diffusivities from element (ox-1, oy-1),
+// all loads issued before the first store
+template <typename TC, int W, int HM, int NT>
+__device__ __forceinline__ void flat_kappa(TC* K, const TC* __restrict__ kap, int ox, int oy, const Geom& g) {
+  constexpr int CNT = (W + 1) * (HM + 1), NL = (CNT + NT - 1) / NT;
+  TC v[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    const int b = idx / (W + 1), a = idx - b * (W + 1);
+    const int ex = ox - 1 + a, ey = oy - 1 + b;
+    const bool ok = idx < CNT && ex >= 0 && ex < g.N && ey >= 0 && ey < g.N;
+    const TC x = kap[ok ? (long)ey * g.pitch + ex : 0];
+    v[r] = ok ? x : (TC)0;
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx < CNT) K[idx] = v[r];
+  }
+}
+
+// DOWN smoothing on a flat Rx x Ry region (row stride W, at most HM rows) with right-hand side T: Chebyshev from
+// zero, then the residual. Returns through x and r the buffers (of P0, P1) holding x_deg (valid from ring deg - 1)
+// and the residual (valid from ring deg). Ends with a barrier.
+template <typename TC, int W, int HM, int NT>
+__device__ void flat_down(const TC* T, TC* P0, TC* P1, const TC* K, int Rx, int Ry, int ox, int oy, int N,
+                          const MGCoef& cf, TC*& x, TC*& r) {
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, c0 = (TC)cf.c0;
+  for (int idx = threadIdx.x; idx < W * HM; idx += NT) {
+    const int lj = idx / W, li = idx - lj * W;
+    if (li >= Rx || lj >= Ry) continue;
+    const int q = lj * (W + 1) + li;
+    TC v = (TC)0;
+    if (interior(ox + li, oy + lj, N)) {
+      const TC D = (TC)16 * m + alpha * (TC)(2.0 / 3.0) * (K[q] + K[q + 1] + K[q + W + 1] + K[q + W + 2]);
+      v = c0 * T[idx] * recip(D);
+    }
+    P0[idx] = v;
+    P1[idx] = (TC)0;
+  }
+  __syncthreads();
+  TC* cur = P0;
+  TC* prv = P1;
+  for (int k = 1; k < cf.deg; ++k) {
+    const TC beta = (TC)cf.beta[k], gam = (TC)cf.gam[k];
+    for (int idx = threadIdx.x; idx < W * HM; idx += NT) {
+      const int lj = idx / W, li = idx - lj * W;
+      if (li < k || li >= Rx - k || lj < k || lj >= Ry - k || !interior(ox + li, oy + lj, N)) continue;
+      TC D;
+      const TC bx = flat_bx<TC, W>(cur, K, li, lj, m, alpha, D);
+      prv[idx] = cur[idx] + beta * (cur[idx] - prv[idx]) + gam * (T[idx] - bx) * recip(D);
+    }
+    __syncthreads();
+    TC* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  const int dg = cf.deg;
+  for (int idx = threadIdx.x; idx < W * HM; idx += NT) {
+    const int lj = idx / W, li = idx - lj * W;
+    if (li < dg || li >= Rx - dg || lj < dg || lj >= Ry - dg) continue;
+    TC v = (TC)0;
+    if (interior(ox + li, oy + lj, N)) {
+      TC D;
+      v = T[idx] - flat_bx<TC, W>(cur, K, li, lj, m, alpha, D);
+    }
+    prv[idx] = v;
+  }
+  __syncthreads();
+  x = cur;
+  r = prv;
+}
+
+// UP smoothing on a flat Rx x Ry region from x0 in P0 (Chebyshev steps with right-hand side T). Returns the buffer
+// holding the result (valid from ring deg). Ends with a barrier.
+template <typename TC, int W, int HM, int NT>
+__device__ TC* flat_up(const TC* T, TC* P0, TC* P1, const TC* K, int Rx, int Ry, int ox, int oy, int N,
+                       const MGCoef& cf) {
+  const TC m = (TC)cf.m, alpha = (TC)cf.alpha, c0 = (TC)cf.c0;
+  for (int idx = threadIdx.x; idx < W * HM; idx += NT) {
+    const int lj = idx / W, li = idx - lj * W;
+    if (li < 1 || li >= Rx - 1 || lj < 1 || lj >= Ry - 1) continue;
+    TC v = (TC)0;
+    if (interior(ox + li, oy + lj, N)) {
+      TC D;
+      const TC bx = flat_bx<TC, W>(P0, K, li, lj, m, alpha, D);
+      v = P0[idx] + c0 * (T[idx] - bx) * recip(D);
+    }
+    P1[idx] = v;
+  }
+  __syncthreads();
+  TC* cur = P1;
+  TC* prv = P0;
+  for (int k = 1; k < cf.deg; ++k) {
+    const TC beta = (TC)cf.beta[k], gam = (TC)cf.gam[k];
+    for (int idx = threadIdx.x; idx < W * HM; idx += NT) {
+      const int lj = idx / W, li = idx - lj * W;
+      if (li < k + 1 || li >= Rx - k - 1 || lj < k + 1 || lj >= Ry - k - 1 || !interior(ox + li, oy + lj, N))
+        continue;
+      TC D;
+      const TC bx = flat_bx<TC, W>(cur, K, li, lj, m, alpha, D);
+      prv[idx] = cur[idx] + beta * (cur[idx] - prv[idx]) + gam * (T[idx] - bx) * recip(D);
+    }
+    __syncthreads();
+    TC* tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  return cur;
+}
+
+// full weighting of the residual region R (row stride W, level origin (ox, oy)) at coarse node (I, J)
+template <typename TC, int W>
+__device__ __forceinline__ TC flat_restrict(const TC* R, int ox, int oy, int I, int J) {
+  const TC* c = R + (2 * J - oy) * W + (2 * I - ox);
+  return c[0] + (TC)0.5 * (c[1] + c[-1] + c[W] + c[-W]) + (TC)0.25 * (c[W + 1] + c[W - 1] + c[-W + 1] + c[-W - 1]);
+}
+
+// bilinear interpolation at fine node (i, j) of a coarse field stored flat (row stride W, level origin (ox, oy))
+template <typename TC, int W>
+__device__ __forceinline__ TC flat_prolong(const TC* E, int ox, int oy, int i, int j) {
+  const TC* b = E + ((j >> 1) - oy) * W + ((i >> 1) - ox);
+  const TC wx = (i & 1) ? (TC)0.5 : (TC)0, wy = (j & 1) ? (TC)0.5 : (TC)0;
+  return ((TC)1 - wx) * ((TC)1 - wy) * b[0] + wx * ((TC)1 - wy) * b[1] + ((TC)1 - wx) * wy * b[W] + wx * wy * b[W + 1];
+}
+
+// DOWN3 geometry: C tile CT (even), flat regions RC, RB, the A region RA <= 64 columns
+template <int DEG>
+struct Down3 {
+  static constexpr int H = DEG + 1;
+  static constexpr int CT = ((WL - 8 * H - 6 * DEG - 3) / 4) & ~1;
+  static constexpr int RC = CT + 2 * H, RB = 2 * RC + 1 + 2 * DEG, RA = 2 * RB + 1 + 2 * DEG;
+  static_assert(CT >= 2 && RA <= WL, "three-level region does not fit");
+};
+
+template <typename TS, typename TC, int DEG, int NW, int RW>
+__global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__ tA, TS* __restrict__ xA,
+                                                          TS* __restrict__ tB, TS* __restrict__ xB,
+                                                          TS* __restrict__ tC, TS* __restrict__ xC,
+                                                          TS* __restrict__ tD, const TC* __restrict__ kA,
+                                                          const TC* __restrict__ kB, const TC* __restrict__ kC,
+                                                          Geom gA, Geom gB, Geom gC, Geom gD, MGCoef cA, MGCoef cB,
+                                                          MGCoef cC) {
+  using G = Down3<DEG>;
+  constexpr int NT = NW * WL, RY = NW * RW, H = G::H, CT = G::CT, RC = G::RC, RB = G::RB;
+  static_assert(RY >= G::RA, "three-level region does not fit the rows");
+  using PL = Plane<RY>;
+  __shared__ TC sA[PL::SIZE];
+  __shared__ TC sA2[PL::SIZE];
+  __shared__ TC sKB[(RB + 1) * (RB + 1)];
+  __shared__ TC sTB[RB * RB];
+  __shared__ TC sB0[RB * RB];
+  __shared__ TC sB1[RB * RB];
+  __shared__ TC sKC[(RC + 1) * (RC + 1)];
+  __shared__ TC sTC[RC * RC];
+  __shared__ TC sC0[RC * RC];
+  __shared__ TC sC1[RC * RC];
+  // nested tiles; the tile count follows the A level so that every node of A, B, C and D is covered
+  const int ntx = (gA.N - 1 + 4 * CT - 1) / (4 * CT);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int iC0 = 1 + (tile % ntx) * CT, jC0 = 1 + (tile / ntx) * CT;
+  const int iB0 = 2 * iC0 - 1, jB0 = 2 * jC0 - 1, iA0 = 2 * iB0 - 1, jA0 = 2 * jB0 - 1;
+  const int oCx = iC0 - H, oCy = jC0 - H;
+  const int oBx = 2 * oCx - 1 - DEG, oBy = 2 * oCy - 1 - DEG;
+  const int oAx = 2 * oBx - 1 - DEG, oAy = 2 * oBy - 1 - DEG;
+
+  // ---- level A (column segments)
+  const int l = threadIdx.x & (WL - 1), r0 = (threadIdx.x / WL) * RW;
+  const int i = oAx + l, jf = oAy + r0;
+  const TC m = (TC)cA.m, alpha = (TC)cA.alpha;
+  bool in[RW];
+  long p[RW];
+  TC tv[RW], kw[RW + 1], ke[RW + 1];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    in[r] = interior(i, jf + r, gA.N);
+    p[r] = in[r] ? (long)(jf + r) * gA.pitch + i : 0;
+    tv[r] = ld<TC>(tA + p[r]);
+  }
+  load_kappa_cols<TC, RW>(kA, i, jf, gA, kw, ke);
+  flat_kappa<TC, RB, RB, NT>(sKB, kB, oBx, oBy, gB);
+  flat_kappa<TC, RC, RC, NT>(sKC, kC, oCx, oCy, gC);
+  zero_spare<TC, RY>(sA);
+  zero_spare<TC, RY>(sA2);
+#pragma unroll
+  for (int r = 0; r < RW; ++r) tv[r] = in[r] ? tv[r] : (TC)0;
+  W9<TC> w[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+  TC xc[RW], xp[RW], bx[RW];
+  {
+    const TC c0 = (TC)cA.c0;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      xc[r] = in[r] ? c0 * w[r].dinv * tv[r] : (TC)0;
+      xp[r] = (TC)0;
+    }
+  }
+  TC* cur = sA;
+  TC* nxt = sA2;
+  store_rows<TC, RY, RW>(cur, l, r0, xc);
+  __syncthreads();
+#pragma unroll
+  for (int k = 1; k < DEG; ++k) {
+    const TC beta = (TC)cA.beta[k], gam = (TC)cA.gam[k];
+    apply_b<TC, RY, RW>(cur, l, r0, w, xc, bx);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const TC xn = in[r] ? xc[r] + beta * (xc[r] - xp[r]) + gam * (tv[r] - bx[r]) * w[r].dinv : (TC)0;
+      xp[r] = xc[r];
+      xc[r] = xn;
+    }
+    store_rows<TC, RY, RW>(nxt, l, r0, xc);
+    __syncthreads();
+    TC* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  apply_b<TC, RY, RW>(cur, l, r0, w, xc, bx);
+  {
+    const int ax = iA0 - oAx, ay = jA0 - oAy;
+    const bool col_in_tile = l >= ax && l < ax + 4 * CT;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int rr = r0 + r;
+      if (col_in_tile && rr >= ay && rr < ay + 4 * CT && in[r]) st(xA + p[r], xc[r]);
+      bx[r] = in[r] ? tv[r] - bx[r] : (TC)0;
+    }
+  }
+  store_rows<TC, RY, RW>(nxt, l, r0, bx);
+  __syncthreads();
+  // ---- restriction A -> right-hand side of B on the B region (and to global on the B tile)
+  for (int idx = threadIdx.x; idx < RB * RB; idx += NT) {
+    const int lj = idx / RB, li = idx - lj * RB;
+    const int I = oBx + li, J = oBy + lj;
+    TC v = (TC)0;
+    if (interior(I, J, gB.N)) {
+      const TC* c = nxt + PL::at(2 * J - oAy, 2 * I - oAx);
+      v = c[0] + (TC)0.5 * (c[1] + c[-1] + c[WL] + c[-WL]) +
+          (TC)0.25 * (c[WL + 1] + c[WL - 1] + c[-WL + 1] + c[-WL - 1]);
+      if (I >= iB0 && I < iB0 + 2 * CT && J >= jB0 && J < jB0 + 2 * CT) st(tB + (long)J * gB.pitch + I, v);
+    }
+    sTB[lj * RB + li] = v;
+  }
+  __syncthreads();
+  // ---- level B
+  TC *bxv, *brv;
+  flat_down<TC, RB, RB, NT>(sTB, sB0, sB1, sKB, RB, RB, oBx, oBy, gB.N, cB, bxv, brv);
+  for (int idx = threadIdx.x; idx < 4 * CT * CT; idx += NT) {
+    const int I = iB0 + idx % (2 * CT), J = jB0 + idx / (2 * CT);
+    if (interior(I, J, gB.N)) st(xB + (long)J * gB.pitch + I, bxv[(J - oBy) * RB + (I - oBx)]);
+  }
+  // ---- restriction B -> right-hand side of C on the C region (and to global on the C tile)
+  for (int idx = threadIdx.x; idx < RC * RC; idx += NT) {
+    const int lj = idx / RC, li = idx - lj * RC;
+    const int I = oCx + li, J = oCy + lj;
+    TC v = (TC)0;
+    if (interior(I, J, gC.N)) {
+      v = flat_restrict<TC, RB>(brv, oBx, oBy, I, J);
+      if (I >= iC0 && I < iC0 + CT && J >= jC0 && J < jC0 + CT) st(tC + (long)J * gC.pitch + I, v);
+    }
+    sTC[lj * RC + li] = v;
+  }
+  __syncthreads();
+  // ---- level C
+  TC *cxv, *crv;
+  flat_down<TC, RC, RC, NT>(sTC, sC0, sC1, sKC, RC, RC, oCx, oCy, gC.N, cC, cxv, crv);
+  for (int idx = threadIdx.x; idx < CT * CT; idx += NT) {
+    const int I = iC0 + idx % CT, J = jC0 + idx / CT;
+    if (interior(I, J, gC.N)) st(xC + (long)J * gC.pitch + I, cxv[(J - oCy) * RC + (I - oCx)]);
+  }
+  // ---- restriction C -> right-hand side of D on the D nodes of the C tile
+  for (int idx = threadIdx.x; idx < (CT / 2) * (CT / 2); idx += NT) {
+    const int I = (iC0 + 1) / 2 + idx % (CT / 2), J = (jC0 + 1) / 2 + idx / (CT / 2);
+    if (I > gD.N - 1 || J > gD.N - 1) continue;
+    st(tD + (long)J * gD.pitch + I, flat_restrict<TC, RC>(crv, oCx, oCy, I, J));
+  }
+}
+
+// UP3 geometry: A region of 64 columns x RY rows (tile less DEG halo rings), the largest flat regions of B and C
+template <int DEG, int RY>
+struct Up3 {
+  static constexpr int TA = WL - 2 * DEG, TAY = RY - 2 * DEG;
+  static constexpr int RBM = WL / 2 + 2 * DEG + 3, RBH = RY / 2 + 2 * DEG + 3;
+  static constexpr int RCM = RBM / 2 + 2 * DEG + 3, RCH = RBH / 2 + 2 * DEG + 3;
+};
+
+// t and x of a flat region from global memory (zero outside the interior), optionally x + P e for the coarse
+// correction e one level down; all loads issued before the first store
+template <typename TS, typename TC, int W, int HM, int NT, bool PROLONG>
+__device__ __forceinline__ void flat_load_tx(TC* T, TC* X, const TS* __restrict__ t, const TS* __restrict__ x,
+                                             const TS* __restrict__ e, int Rx, int Ry, int ox, int oy, const Geom& g,
+                                             const Geom& ge) {
+  constexpr int CNT = W * HM, NL = (CNT + NT - 1) / NT;
+  TC tv[NL], xv[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    const int lj = idx / W, li = idx - lj * W;
+    const int I = ox + li, J = oy + lj;
+    const bool ok = idx < CNT && li < Rx && lj < Ry && interior(I, J, g.N);
+    const int Ic = ok ? I : 1, Jc = ok ? J : 1;
+    const long q = (long)Jc * g.pitch + Ic;
+    const TC a = ld<TC>(t + q);
+    TC b = ld<TC>(x + q);
+    if (PROLONG) b += prolong_at<TS, TC>(e, ge.pitch, Ic, Jc);
+    tv[r] = ok ? a : (TC)0;
+    xv[r] = ok ? b : (TC)0;
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx < CNT) {
+      T[idx] = tv[r];
+      X[idx] = xv[r];
+    }
+  }
+}
+
+template <typename TS, typename TC, int DEG, int NW, int RW>
+__global__ __launch_bounds__(NW* WL) void mg_up3_kernel(const TS* __restrict__ eD, const TS* __restrict__ tC,
+                                                        const TS* __restrict__ xC, const TS* __restrict__ tB,
+                                                        const TS* __restrict__ xB, const TS* __restrict__ tA,
+                                                        const TS* __restrict__ xA, TS* __restrict__ outA,
+                                                        const TC* __restrict__ kA, const TC* __restrict__ kB,
+                                                        const TC* __restrict__ kC, Geom gA, Geom gB, Geom gC, Geom gD,
+                                                        MGCoef cA, MGCoef cB, MGCoef cC) {
+  constexpr int NT = NW * WL, RY = NW * RW;
+  using G = Up3<DEG, RY>;
+  constexpr int TA = G::TA, TAY = G::TAY, RBM = G::RBM, RBH = G::RBH, RCM = G::RCM, RCH = G::RCH;
+  using PL = Plane<RY>;
+  __shared__ TC sA[PL::SIZE];
+  __shared__ TC sA2[PL::SIZE];
+  __shared__ TC sKB[(RBM + 1) * (RBH + 1)];
+  __shared__ TC sTB[RBM * RBH];
+  __shared__ TC sB0[RBM * RBH];
+  __shared__ TC sB1[RBM * RBH];
+  __shared__ TC sKC[(RCM + 1) * (RCH + 1)];
+  __shared__ TC sTC[RCM * RCH];
+  __shared__ TC sC0[RCM * RCH];
+  __shared__ TC sC1[RCM * RCH];
+  const int ntx = (gA.N - 1 + TA - 1) / TA;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int iA0 = 1 + (tile % ntx) * TA, jA0 = 1 + (tile / ntx) * TAY;
+  const int oAx = iA0 - DEG, oAy = jA0 - DEG;
+  // B nodes whose result the A region's prolongation reads, and the B region (DEG rings more) that produces them
+  const int bLx = oAx >> 1, bLy = oAy >> 1;
+  const int oBx = bLx - DEG, oBy = bLy - DEG;
+  const int RBx = ((oAx + WL - 1) >> 1) + 2 - bLx + 2 * DEG, RBy = ((oAy + RY - 1) >> 1) + 2 - bLy + 2 * DEG;
+  // the same one level down
+  const int cLx = oBx >> 1, cLy = oBy >> 1;
+  const int oCx = cLx - DEG, oCy = cLy - DEG;
+  const int RCx = ((oBx + RBx - 1) >> 1) + 2 - cLx + 2 * DEG, RCy = ((oBy + RBy - 1) >> 1) + 2 - cLy + 2 * DEG;
+
+  // ---- loads: A rows (column segments), the B and C regions (flat), their diffusivities
+  const int l = threadIdx.x & (WL - 1), r0 = (threadIdx.x / WL) * RW;
+  const int i = oAx + l, jf = oAy + r0;
+  bool in[RW];
+  long p[RW];
+  TC tv[RW], xa[RW], kw[RW + 1], ke[RW + 1];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    in[r] = interior(i, jf + r, gA.N);
+    p[r] = in[r] ? (long)(jf + r) * gA.pitch + i : 0;
+    tv[r] = ld<TC>(tA + p[r]);
+    xa[r] = ld<TC>(xA + p[r]);
+  }
+  load_kappa_cols<TC, RW>(kA, i, jf, gA, kw, ke);
+  flat_kappa<TC, RBM, RBH, NT>(sKB, kB, oBx, oBy, gB);
+  flat_kappa<TC, RCM, RCH, NT>(sKC, kC, oCx, oCy, gC);
+  flat_load_tx<TS, TC, RBM, RBH, NT, false>(sTB, sB1, tB, xB, nullptr, RBx, RBy, oBx, oBy, gB, gC);
+  flat_load_tx<TS, TC, RCM, RCH, NT, true>(sTC, sC0, tC, xC, eD, RCx, RCy, oCx, oCy, gC, gD);
+  __syncthreads();
+  // ---- level C: post-smoothing from x_C + P e_D
+  const TC* cout = flat_up<TC, RCM, RCH, NT>(sTC, sC0, sC1, sKC, RCx, RCy, oCx, oCy, gC.N, cC);
+  // ---- level B: x_B + P (C result), post-smoothing
+  for (int idx = threadIdx.x; idx < RBM * RBH; idx += NT) {
+    const int lj = idx / RBM, li = idx - lj * RBM;
+    if (li >= RBx || lj >= RBy) continue;
+    const int I = oBx + li, J = oBy + lj;
+    TC v = (TC)0;
+    if (interior(I, J, gB.N)) v = sB1[idx] + flat_prolong<TC, RCM>(cout, oCx, oCy, I, J);
+    sB0[idx] = v;
+  }
+  __syncthreads();
+  const TC* bout = flat_up<TC, RBM, RBH, NT>(sTB, sB0, sB1, sKB, RBx, RBy, oBx, oBy, gB.N, cB);
+  // ---- level A: x_A + P (B result), post-smoothing in column segments, result on the A tile
+  const TC m = (TC)cA.m, alpha = (TC)cA.alpha;
+  W9<TC> w[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+  TC xc[RW], xp[RW], bx[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) xp[r] = in[r] ? xa[r] + flat_prolong<TC, RBM>(bout, oBx, oBy, i, jf + r) : (TC)0;
+  zero_spare<TC, RY>(sA);
+  zero_spare<TC, RY>(sA2);
+  store_rows<TC, RY, RW>(sA, l, r0, xp);
+  __syncthreads();
+  apply_b<TC, RY, RW>(sA, l, r0, w, xp, bx);
+  {
+    const TC c0 = (TC)cA.c0;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) xc[r] = in[r] ? xp[r] + c0 * (tv[r] - bx[r]) * w[r].dinv : (TC)0;
+  }
+  TC* cur = sA;
+  TC* nxt = sA2;
+#pragma unroll
+  for (int k = 1; k < DEG; ++k) {
+    store_rows<TC, RY, RW>(nxt, l, r0, xc);
+    __syncthreads();
+    TC* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    const TC beta = (TC)cA.beta[k], gam = (TC)cA.gam[k];
+    apply_b<TC, RY, RW>(cur, l, r0, w, xc, bx);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const TC xn = in[r] ? xc[r] + beta * (xc[r] - xp[r]) + gam * (tv[r] - bx[r]) * w[r].dinv : (TC)0;
+      xp[r] = xc[r];
+      xc[r] = xn;
+    }
+  }
+  const bool col_in_tile = l >= DEG && l < WL - DEG;
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int rr = r0 + r;
+    if (col_in_tile && rr >= DEG && rr < RY - DEG && in[r]) st(outA + p[r], xc[r]);
+  }
+}
+
 // Coarsest level: out = Binv * t on the n = (N-1)^2 <= 1024 interior nodes. One wavefront per
 // row; each lane issues all of its (at most 16) coalesced row loads and right-hand-side loads
 // before accumulating, then a fixed-order wavefront reduction.
@@ -479,6 +937,61 @@ void up_t(const void* t, const void* x, const void* e, void* out, const void* ka
                                        st);
 }
 
+// three-level kernels: DOWN3 on 64-row A regions of 16 wavefronts with 4 rows per lane (the nested tiles need the
+// height); UP3 on 32-row regions of 8 wavefronts, twice the blocks
+constexpr int NW3 = 16, RW3 = 4, NWU3 = 8, RWU3 = 4;
+
+template <typename TS, typename TC>
+void down3_t(const ThreeLevels& z, hipStream_t st) {
+  const Geom& gA = z.g[0];
+  auto grid = [&](int ct) { const int n = (gA.N - 1 + 4 * ct - 1) / (4 * ct); return dim3(n * n); };
+  const TS* tA = (const TS*)z.t[0];
+  TS *xA = (TS*)z.x[0], *tB = (TS*)z.t[1], *xB = (TS*)z.x[1], *tC = (TS*)z.t[2], *xC = (TS*)z.x[2], *tD = (TS*)z.t[3];
+  const TC *kA = (const TC*)z.kap[0], *kB = (const TC*)z.kap[1], *kC = (const TC*)z.kap[2];
+  switch (z.c[0].deg) {
+    case 1:
+      launch_k(mg_down3_kernel<TS, TC, 1, NW3, RW3>, grid(Down3<1>::CT), dim3(NW3 * WL), st, tA, xA, tB, xB, tC, xC, tD,
+               kA, kB, kC, z.g[0], z.g[1], z.g[2], z.g[3], z.c[0], z.c[1], z.c[2]);
+      break;
+    case 2:
+      launch_k(mg_down3_kernel<TS, TC, 2, NW3, RW3>, grid(Down3<2>::CT), dim3(NW3 * WL), st, tA, xA, tB, xB, tC, xC, tD,
+               kA, kB, kC, z.g[0], z.g[1], z.g[2], z.g[3], z.c[0], z.c[1], z.c[2]);
+      break;
+    default:
+      launch_k(mg_down3_kernel<TS, TC, 3, NW3, RW3>, grid(Down3<3>::CT), dim3(NW3 * WL), st, tA, xA, tB, xB, tC, xC, tD,
+               kA, kB, kC, z.g[0], z.g[1], z.g[2], z.g[3], z.c[0], z.c[1], z.c[2]);
+      break;
+  }
+}
+
+template <typename TS, typename TC>
+void up3_t(const ThreeLevels& z, hipStream_t st) {
+  const Geom& gA = z.g[0];
+  auto grid = [&](int deg) {
+    const int tx = WL - 2 * deg, ty = NWU3 * RWU3 - 2 * deg;
+    return dim3(((gA.N - 1 + tx - 1) / tx) * ((gA.N - 1 + ty - 1) / ty));
+  };
+  const TS* eD = (const TS*)z.e[3];
+  const TS *tC = (const TS*)z.t[2], *xC = (const TS*)z.x[2], *tB = (const TS*)z.t[1], *xB = (const TS*)z.x[1];
+  const TS *tA = (const TS*)z.t[0], *xA = (const TS*)z.x[0];
+  TS* outA = (TS*)z.e[0];
+  const TC *kA = (const TC*)z.kap[0], *kB = (const TC*)z.kap[1], *kC = (const TC*)z.kap[2];
+  switch (z.c[0].deg) {
+    case 1:
+      launch_k(mg_up3_kernel<TS, TC, 1, NWU3, RWU3>, grid(1), dim3(NWU3 * WL), st, eD, tC, xC, tB, xB, tA, xA, outA, kA, kB,
+               kC, z.g[0], z.g[1], z.g[2], z.g[3], z.c[0], z.c[1], z.c[2]);
+      break;
+    case 2:
+      launch_k(mg_up3_kernel<TS, TC, 2, NWU3, RWU3>, grid(2), dim3(NWU3 * WL), st, eD, tC, xC, tB, xB, tA, xA, outA, kA, kB,
+               kC, z.g[0], z.g[1], z.g[2], z.g[3], z.c[0], z.c[1], z.c[2]);
+      break;
+    default:
+      launch_k(mg_up3_kernel<TS, TC, 3, NWU3, RWU3>, grid(3), dim3(NWU3 * WL), st, eD, tC, xC, tB, xB, tA, xA, outA, kA, kB,
+               kC, z.g[0], z.g[1], z.g[2], z.g[3], z.c[0], z.c[1], z.c[2]);
+      break;
+  }
+}
+
 }  // namespace
 
 void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, void* tout,
@@ -532,6 +1045,24 @@ void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tsc
     launch_k(mg_coarse_kernel<bf16, bf16, float>, grid, NTC, st, (const bf16*)t, tscale, (bf16*)out, (const float*)Binv,
                                                             g);
   }
+}
+
+void launch_mg_down3(int prec, const ThreeLevels& z, hipStream_t st) {
+  if (prec == 0)
+    down3_t<double, double>(z, st);
+  else if (prec == 1)
+    down3_t<float, float>(z, st);
+  else
+    down3_t<bf16, float>(z, st);
+}
+
+void launch_mg_up3(int prec, const ThreeLevels& z, hipStream_t st) {
+  if (prec == 0)
+    up3_t<double, double>(z, st);
+  else if (prec == 1)
+    up3_t<float, float>(z, st);
+  else
+    up3_t<bf16, float>(z, st);
 }
 
 }  // namespace irk

@@ -265,6 +265,33 @@ Bytes mg_up_bytes(const irk_stepper* st, int l) {
   return {n * (8.25 * p + 2 * c), n * (tin + p + 0.25 * p + c + out)};
 }
 
+// three levels A = a, a+1, a+2 in one launch: the per-pass model of the three single-level kernels; the fused
+// minimum reads A's right-hand side and the three diffusivities, writes the three iterates and the right-hand
+// sides of B, C and D (the intermediate right-hand sides are not read back)
+Bytes mg_down3_bytes(const irk_stepper* st, int a) {
+  const double p = (double)storage_bytes(st->prec), c = compute_bytes(st);
+  Bytes b{0, 0};
+  for (int q = 0; q < 3; ++q) {
+    const double n = nodes(st->lv[a + q].g);
+    b.model += mg_down_bytes(st, a + q, 0).model;
+    b.min += n * ((q == 0 ? p : 0.0) + c + p + 0.25 * p);
+  }
+  return b;
+}
+
+// the converse: reads D's correction, the right-hand sides, iterates and diffusivities of the three levels and
+// writes A's result (the intermediate results stay in the block)
+Bytes mg_up3_bytes(const irk_stepper* st, int a) {
+  const double p = (double)storage_bytes(st->prec), c = compute_bytes(st);
+  Bytes b{0, 0};
+  for (int q = 0; q < 3; ++q) {
+    const double n = nodes(st->lv[a + q].g);
+    b.model += mg_up_bytes(st, a + q).model;
+    b.min += n * (2 * p + c + (q == 0 ? p : 0.0) + (q == 2 ? 0.25 * p : 0.0));
+  }
+  return b;
+}
+
 // dense coarsest solve on nv unknowns: the inverse once, the right-hand side and the result
 Bytes coarse_bytes(const irk_stepper* st, double nv, bool io64) {
   const double c = compute_bytes(st), io = io64 ? 16.0 : 2.0 * (double)storage_bytes(st->prec);
@@ -697,17 +724,42 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
     return check_launch();
   }
   std::vector<Level>& lv = st->lv;
+  // the three levels above the coarsest run as one DOWN and one UP launch when they are not the finest level
+  const int A3 = L - 4;
+  const bool three = A3 >= 1;
+  ThreeLevels z{};
+  if (three) {
+    for (int q = 0; q < 4; ++q) {
+      const Level& lq = lv[A3 + q];
+      z.g[q] = lq.g;
+      z.t[q] = lq.t;
+      z.e[q] = lq.e;
+      if (q < 3) {
+        z.c[q] = cf[A3 + q];
+        z.x[q] = lq.x;
+        z.kap[q] = lq.kapc;
+      }
+    }
+  }
   // the finest DOWN stores the right-hand side it smoothed (scaled, with the stage coupling) for the finest UP
   CHK(arm(st, IRK_KFAM_MG_FINE, mg_down_bytes(st, 0, cp.nz)));
   launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].tp, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
-  for (int l = 1; l < L - 1; ++l) {
+  for (int l = 1; l < (three ? A3 : L - 1); ++l) {
     CHK(arm(st, IRK_KFAM_MG_COARSE, mg_down_bytes(st, l, 0)));
     launch_mg_down(pr, false, lv[l].t, nullptr, lv[l].x, lv[l + 1].t, nullptr, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l],
                    none, s);
   }
+  if (three) {
+    CHK(arm(st, IRK_KFAM_MG_COARSE, mg_down3_bytes(st, A3)));
+    launch_mg_down3(pr, z, s);
+  }
   CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nodes(lv[L - 1].g), false)));
   launch_mg_coarse(pr, false, lv[L - 1].t, nullptr, lv[L - 1].e, st->binv[stage], lv[L - 1].g, s);
-  for (int l = L - 2; l >= 1; --l) {
+  if (three) {
+    CHK(arm(st, IRK_KFAM_MG_COARSE, mg_up3_bytes(st, A3)));
+    launch_mg_up3(pr, z, s);
+  }
+  for (int l = (three ? A3 - 1 : L - 2); l >= 1; --l) {
     CHK(arm(st, IRK_KFAM_MG_COARSE, mg_up_bytes(st, l)));
     launch_mg_up(pr, false, lv[l].t, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
   }

@@ -11,9 +11,11 @@ from gpu_util import dev, host, make, rel
 pytestmark = pytest.mark.gpu
 
 
+# five or more levels run the three levels above the coarsest in one DOWN and one UP launch (N = 96, 128 with
+# coarse_n = 8, every Chebyshev degree); fewer levels one launch per level
 @pytest.mark.parametrize("N,dt,deg,cn", [(64, 1e-3, 2, 8), (96, 1e-3, 2, 8), (128, 5e-4, 2, 8), (32, 1.0 / 32, 2, 8),
                                          (64, 1e-3, 1, 8), (64, 1e-3, 3, 8), (8, 1e-3, 2, 8), (256, 1e-3, 2, 32),
-                                         (96, 1e-3, 2, 32), (66, 1e-3, 2, 32)])
+                                         (96, 1e-3, 2, 32), (66, 1e-3, 2, 32), (128, 1e-3, 1, 8), (128, 1e-3, 3, 8)])
 def test_vcycle_fp64_matches_oracle(N, dt, deg, cn):
     kap = synth.grf_kappa(N, 1)
     otab = OT.radau_iia(3)
