@@ -115,8 +115,8 @@ __device__ __forceinline__ void load_kappa_cols(const TC* __restrict__ kap, int 
     const int ey = jfirst - 1 + q;
     const bool oky = ey >= 0 && ey < g.N;
     const bool okw = oky && i - 1 >= 0 && i - 1 < g.N, oke = oky && i >= 0 && i < g.N;
-    const TC a = kap[okw ? (long)ey * g.pitch + i - 1 : 0];
-    const TC b = kap[oke ? (long)ey * g.pitch + i : 0];
+    const TC a = kap[okw ? (unsigned)ey * g.pitch + i - 1 : 0];
+    const TC b = kap[oke ? (unsigned)ey * g.pitch + i : 0];
     kw[q] = okw ? a : (TC)0;
     ke[q] = oke ? b : (TC)0;
   }
@@ -185,12 +185,12 @@ __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ 
   const TC ts = (TC)((tscale ? *tscale : 1.0) * cp.vmul);
 
   bool in[RW];
-  long p[RW];
+  unsigned p[RW];
   TC tv[RW], kw[RW + 1], ke[RW + 1], wv[RW];
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, N);
-    p[r] = in[r] ? (long)(jf + r) * g.pitch + i : 0;
+    p[r] = in[r] ? (unsigned)(jf + r) * g.pitch + i : 0;
     tv[r] = ld<TC>(t + p[r]);
   }
   load_kappa_cols<TC, RW>(kap, i, jf, g, kw, ke);
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ 
       const TC* R = nxt + PL::at(2 * J - oy, 2 * I - ox);
       const TC v = R[0] + (TC)0.5 * (R[1] + R[-1] + R[WL] + R[-WL]) +
                    (TC)0.25 * (R[WL + 1] + R[WL - 1] + R[-WL + 1] + R[-WL - 1]);
-      st(tc + (long)J * gc.pitch + I, v);
+      st(tc + (unsigned)J * gc.pitch + I, v);
     }
   }
 }
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(NW* WL) void mg_up_kernel(const TT* __restrict__ t,
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, N);
     const int ic = in[r] ? i : 1, jc = in[r] ? jf + r : 1;
-    const long p = (long)jc * g.pitch + ic;
+    const unsigned p = (unsigned)jc * g.pitch + ic;
     const TC a = ld<TC>(t + p);
     const TC b = ld<TC>(x + p) + prolong_at<TS, TC>(e, gc.pitch, ic, jc);
     tv[r] = in[r] ? a : (TC)0;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(NW* WL) void mg_up_kernel(const TT* __restrict__ t,
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     const int rr = r0 + r;
-    if (col_in_tile && rr >= H && rr < RY - H && in[r]) st(out + (long)(jf + r) * g.pitch + i, xc[r]);
+    if (col_in_tile && rr >= H && rr < RY - H && in[r]) st(out + (unsigned)(jf + r) * g.pitch + i, xc[r]);
   }
 }
 
@@ -399,7 +399,7 @@ __device__ __forceinline__ void flat_kappa(TC* K, const TC* __restrict__ kap, in
     const int b = idx / (W + 1), a = idx - b * (W + 1);
     const int ex = ox - 1 + a, ey = oy - 1 + b;
     const bool ok = idx < CNT && ex >= 0 && ex < g.N && ey >= 0 && ey < g.N;
-    const TC x = kap[ok ? (long)ey * g.pitch + ex : 0];
+    const TC x = kap[ok ? (unsigned)ey * g.pitch + ex : 0];
     v[r] = ok ? x : (TC)0;
   }
 #pragma unroll
@@ -559,12 +559,12 @@ __global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__
   const int i = oAx + l, jf = oAy + r0;
   const TC m = (TC)cA.m, alpha = (TC)cA.alpha;
   bool in[RW];
-  long p[RW];
+  unsigned p[RW];
   TC tv[RW], kw[RW + 1], ke[RW + 1];
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, gA.N);
-    p[r] = in[r] ? (long)(jf + r) * gA.pitch + i : 0;
+    p[r] = in[r] ? (unsigned)(jf + r) * gA.pitch + i : 0;
     tv[r] = ld<TC>(tA + p[r]);
   }
   load_kappa_cols<TC, RW>(kA, i, jf, gA, kw, ke);
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__
       const TC* c = nxt + PL::at(2 * J - oAy, 2 * I - oAx);
       v = c[0] + (TC)0.5 * (c[1] + c[-1] + c[WL] + c[-WL]) +
           (TC)0.25 * (c[WL + 1] + c[WL - 1] + c[-WL + 1] + c[-WL - 1]);
-      if (I >= iB0 && I < iB0 + 2 * CT && J >= jB0 && J < jB0 + 2 * CT) st(tB + (long)J * gB.pitch + I, v);
+      if (I >= iB0 && I < iB0 + 2 * CT && J >= jB0 && J < jB0 + 2 * CT) st(tB + (unsigned)J * gB.pitch + I, v);
     }
     sTB[lj * RB + li] = v;
   }
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__
   flat_down<TC, RB, RB, NT>(sTB, sB0, sB1, sKB, RB, RB, oBx, oBy, gB.N, cB, bxv, brv);
   for (int idx = threadIdx.x; idx < 4 * CT * CT; idx += NT) {
     const int I = iB0 + idx % (2 * CT), J = jB0 + idx / (2 * CT);
-    if (interior(I, J, gB.N)) st(xB + (long)J * gB.pitch + I, bxv[(J - oBy) * RB + (I - oBx)]);
+    if (interior(I, J, gB.N)) st(xB + (unsigned)J * gB.pitch + I, bxv[(J - oBy) * RB + (I - oBx)]);
   }
   // ---- restriction B -> right-hand side of C on the C region (and to global on the C tile)
   for (int idx = threadIdx.x; idx < RC * RC; idx += NT) {
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__
     TC v = (TC)0;
     if (interior(I, J, gC.N)) {
       v = flat_restrict<TC, RB>(brv, oBx, oBy, I, J);
-      if (I >= iC0 && I < iC0 + CT && J >= jC0 && J < jC0 + CT) st(tC + (long)J * gC.pitch + I, v);
+      if (I >= iC0 && I < iC0 + CT && J >= jC0 && J < jC0 + CT) st(tC + (unsigned)J * gC.pitch + I, v);
     }
     sTC[lj * RC + li] = v;
   }
@@ -657,13 +657,13 @@ __global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__
   flat_down<TC, RC, RC, NT>(sTC, sC0, sC1, sKC, RC, RC, oCx, oCy, gC.N, cC, cxv, crv);
   for (int idx = threadIdx.x; idx < CT * CT; idx += NT) {
     const int I = iC0 + idx % CT, J = jC0 + idx / CT;
-    if (interior(I, J, gC.N)) st(xC + (long)J * gC.pitch + I, cxv[(J - oCy) * RC + (I - oCx)]);
+    if (interior(I, J, gC.N)) st(xC + (unsigned)J * gC.pitch + I, cxv[(J - oCy) * RC + (I - oCx)]);
   }
   // ---- restriction C -> right-hand side of D on the D nodes of the C tile
   for (int idx = threadIdx.x; idx < (CT / 2) * (CT / 2); idx += NT) {
     const int I = (iC0 + 1) / 2 + idx % (CT / 2), J = (jC0 + 1) / 2 + idx / (CT / 2);
     if (I > gD.N - 1 || J > gD.N - 1) continue;
-    st(tD + (long)J * gD.pitch + I, flat_restrict<TC, RC>(crv, oCx, oCy, I, J));
+    st(tD + (unsigned)J * gD.pitch + I, flat_restrict<TC, RC>(crv, oCx, oCy, I, J));
   }
 }
 
@@ -690,7 +690,7 @@ __device__ __forceinline__ void flat_load_tx(TC* T, TC* X, const TS* __restrict_
     const int I = ox + li, J = oy + lj;
     const bool ok = idx < CNT && li < Rx && lj < Ry && interior(I, J, g.N);
     const int Ic = ok ? I : 1, Jc = ok ? J : 1;
-    const long q = (long)Jc * g.pitch + Ic;
+    const unsigned q = (unsigned)Jc * g.pitch + Ic;
     const TC a = ld<TC>(t + q);
     TC b = ld<TC>(x + q);
     if (PROLONG) b += prolong_at<TS, TC>(e, ge.pitch, Ic, Jc);
@@ -746,12 +746,12 @@ __global__ __launch_bounds__(NW* WL) void mg_up3_kernel(const TS* __restrict__ e
   const int l = threadIdx.x & (WL - 1), r0 = (threadIdx.x / WL) * RW;
   const int i = oAx + l, jf = oAy + r0;
   bool in[RW];
-  long p[RW];
+  unsigned p[RW];
   TC tv[RW], xa[RW], kw[RW + 1], ke[RW + 1];
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, gA.N);
-    p[r] = in[r] ? (long)(jf + r) * gA.pitch + i : 0;
+    p[r] = in[r] ? (unsigned)(jf + r) * gA.pitch + i : 0;
     tv[r] = ld<TC>(tA + p[r]);
     xa[r] = ld<TC>(xA + p[r]);
   }

@@ -147,9 +147,10 @@ __global__ void coarsen_kappa_kernel(const double* __restrict__ f, double* __res
 // of every 9-point stencil and the element diffusivities are loaded once per column segment
 // ((RB + 2) * 3 values per plane and 2 (RB + 1) diffusivities for RB nodes); tiles in XCD-aware order.
 constexpr int RB = 4;
+constexpr int SBY = 4;  // wavefronts per block
 
 template <int S, bool IA>
-__global__ __launch_bounds__(BX* BY) void stage_operator_kernel(const double* __restrict__ x, double* __restrict__ y,
+__global__ __launch_bounds__(BX* SBY) void stage_operator_kernel(const double* __restrict__ x, double* __restrict__ y,
                                                                 const double* __restrict__ f,
                                                                 const double* __restrict__ kap, Geom g, Coefs a,
                                                                 double dt) {
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(BX* BY) void stage_operator_kernel(const double* __
   const int ntx = (N - 1 + BX - 1) / BX;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int i = 1 + (t % ntx) * BX + threadIdx.x;
-  const int j0 = 1 + (t / ntx) * (BY * RB) + threadIdx.y * RB;
+  const int j0 = 1 + (t / ntx) * (SBY * RB) + threadIdx.y * RB;
   if (i > N - 1 || j0 > N - 1) return;
   const double m = g.h * g.h / 36.0;
   // element rows j0-1 .. j0+RB-1 and node rows j0-1 .. j0+RB, clamped to the array (values past the
@@ -411,8 +412,8 @@ void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, 
 template <bool IA>
 void stage_operator_t(const double* x, double* y, const double* f, const double* kappa, Geom g, int s, const Coefs& a,
                       double dt, hipStream_t st) {
-  const int ntx = (g.N - 1 + BX - 1) / BX, nty = (g.N - 1 + BY * RB - 1) / (BY * RB);
-  const dim3 grid(ntx * nty), blk(BX, BY);
+  const int ntx = (g.N - 1 + BX - 1) / BX, nty = (g.N - 1 + SBY * RB - 1) / (SBY * RB);
+  const dim3 grid(ntx * nty), blk(BX, SBY);
   switch (s) {
     case 1: launch_k(stage_operator_kernel<1, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
     case 2: launch_k(stage_operator_kernel<2, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;

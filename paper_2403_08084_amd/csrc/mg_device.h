@@ -41,8 +41,11 @@ __device__ __forceinline__ bool interior(int i, int j, int N) { return i >= 1 &&
 // weights 1, 1/2, 1/4 by parity; all four coarse values are loaded (always in bounds)
 template <typename TS, typename TC>
 __device__ __forceinline__ TC prolong_at(const TS* __restrict__ e, int pc, int i, int j) {
-  const TS* b = e + (long)(j >> 1) * pc + (i >> 1);
-  const TC e00 = ld<TC>(b), e10 = ld<TC>(b + 1), e01 = ld<TC>(b + pc), e11 = ld<TC>(b + pc + 1);
+  // a 32-bit element offset from the (uniform) base, then constant offsets from the two row pointers: the
+  // compiler can pair the loads of horizontally adjacent values
+  const TS* q0 = e + ((unsigned)(j >> 1) * (unsigned)pc + (unsigned)(i >> 1));
+  const TS* q1 = q0 + pc;
+  const TC e00 = ld<TC>(q0), e10 = ld<TC>(q0 + 1), e01 = ld<TC>(q1), e11 = ld<TC>(q1 + 1);
   const TC wx = (i & 1) ? (TC)0.5 : (TC)0, wy = (j & 1) ? (TC)0.5 : (TC)0;
   return ((TC)1 - wx) * ((TC)1 - wy) * e00 + wx * ((TC)1 - wy) * e10 + ((TC)1 - wx) * wy * e01 + wx * wy * e11;
 }
@@ -60,7 +63,7 @@ __device__ __forceinline__ void load_kappa_tile(TC* sK, const TK* __restrict__ k
     const int ex = ox - 1 + a, ey = oy - 1 + b;
     const bool ok = idx < CNT && ex >= 0 && ex < g.N && ey >= 0 && ey < g.N;
     // unconditional load from a clamped address keeps all loads in flight; the select zeroes the rest
-    const TC val = (TC)kap[ok ? (long)ey * g.pitch + ex : 0];
+    const TC val = (TC)kap[ok ? (unsigned)ey * g.pitch + ex : 0u];
     v[r] = ok ? val : (TC)0;
   }
 #pragma unroll
