@@ -150,6 +150,15 @@ void irk_options_default(irk_options *opts);
 int irk_problem_create(irk_problem **out, int N, const double *kappa, void *stream);
 void irk_problem_destroy(irk_problem *p);
 
+/* Replaces the problem's diffusivity (the kappa of eq:rkheat, Section 2) by kappa (device, N*N
+ * doubles, element (ex, ey) at ey*N + ex), e.g. between the iterations of an optimisation over
+ * kappa. Every value must be finite and > 0: otherwise IRK_EINVAL and the old kappa stays.
+ * Waits for the stream. Steppers built on the problem see the new kappa in their stage operator
+ * at once; their multigrid hierarchy (level diffusivities, Chebyshev estimates, coarsest
+ * inverse) is updated by irk_stepper_refresh, which must be called on each of them before
+ * their next solve. */
+int irk_problem_set_kappa(irk_problem *p, const double *kappa, void *stream);
+
 /* y = M x on one nodal vector: the consistent mass matrix M of eq:rkheat (Section 2),
  * Dirichlet rows and columns removed (device, n doubles each; x and y must not overlap).
  * Used for objectives such as J = 1/2 |u - u_*|_M^2. Staging: two padded planes owned by the
@@ -184,6 +193,13 @@ int irk_apply_mass_noalloc(const irk_problem *p, const double *x, double *y, voi
 int irk_stepper_create(irk_stepper **out, const irk_problem *p, const irk_tableau *tab,
                        double dt, const irk_options *opts, void *stream);
 void irk_stepper_destroy(irk_stepper *st);
+
+/* Rebuilds the kappa-dependent state of a stepper from its problem's current kappa (after
+ * irk_problem_set_kappa): level diffusivities, power-iteration estimates and Chebyshev
+ * coefficients, coarsest-level inverses (also of the monolithic cycle), reusing every
+ * buffer; captured Arnoldi graphs are dropped (captured again on first use) and the next
+ * solve starts without a previous-step guess. Waits for the stream before and after. */
+int irk_stepper_refresh(irk_stepper *st, void *stream);
 
 /* a1 (Section 2, eq:rkheat): f_i = -K u + F for every stage i. u: device n; F: device
  * n or NULL (F = 0); f: device s*n. */
@@ -231,7 +247,9 @@ int irk_advance(irk_stepper *st, double *u, const double *F, int nsteps, irk_sta
  * lambda_T = dJ/du_N (device n) it returns lambda_0 = dJ/du_0 (device n, may be NULL) and
  * grad_logkappa = dJ/dlog(kappa) (device N*N, element layout, may be NULL). The forward
  * states are recomputed from nsnap >= 1 snapshots (one of them u0) by the optimal binomial
- * checkpointing schedule. Synchronises. */
+ * checkpointing schedule. Workspace (min(nsnap, nsteps) checkpoint planes, the adjoint state, the
+ * gradient and two stage vectors) is owned by the stepper: allocated by the first call, the
+ * checkpoint planes grown when a later call needs more. Synchronises. */
 int irk_adjoint(irk_stepper *st, const double *u0, int nsteps, int nsnap, const double *lambda_T,
                 double *lambda_0, double *grad_logkappa, irk_stats *stats, void *stream);
 

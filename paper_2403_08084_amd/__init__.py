@@ -109,10 +109,11 @@ class Stats(ctypes.Structure):
 _lib = None
 
 SYMBOLS = [
-    "irk_last_error", "irk_options_default", "irk_problem_create", "irk_problem_destroy", "irk_apply_mass",
-    "irk_apply_stiffness", "irk_apply_mass_noalloc", "irk_stepper_create", "irk_stepper_destroy", "irk_stage_rhs", "irk_apply_stage_operator",
-    "irk_apply_preconditioner", "irk_vcycle", "irk_solve_stages", "irk_advance", "irk_adjoint",
-    "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu", "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_family", "irk_kernel_timer_read",
+    "irk_last_error", "irk_options_default", "irk_problem_create", "irk_problem_destroy", "irk_problem_set_kappa",
+    "irk_apply_mass", "irk_apply_stiffness", "irk_apply_mass_noalloc", "irk_stepper_create", "irk_stepper_destroy",
+    "irk_stepper_refresh", "irk_stage_rhs", "irk_apply_stage_operator", "irk_apply_preconditioner", "irk_vcycle",
+    "irk_solve_stages", "irk_advance", "irk_adjoint", "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu",
+    "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_family", "irk_kernel_timer_read",
 ]
 
 
@@ -132,6 +133,7 @@ def lib():
     L.irk_problem_create.argtypes = [ctypes.POINTER(vp), ip, vp, vp]
     L.irk_problem_destroy.restype = None
     L.irk_problem_destroy.argtypes = [vp]
+    L.irk_problem_set_kappa.argtypes = [vp, vp, vp]
     L.irk_apply_mass.argtypes = [vp, vp, vp, vp]
     L.irk_apply_stiffness.argtypes = [vp, vp, vp, vp]
     L.irk_apply_mass_noalloc.argtypes = [vp, vp, vp, vp]
@@ -139,6 +141,7 @@ def lib():
                                      ctypes.POINTER(Options), vp]
     L.irk_stepper_destroy.restype = None
     L.irk_stepper_destroy.argtypes = [vp]
+    L.irk_stepper_refresh.argtypes = [vp, vp]
     L.irk_stage_rhs.argtypes = [vp, vp, vp, vp, vp]
     L.irk_apply_stage_operator.argtypes = [vp, vp, vp, ip, vp]
     L.irk_apply_preconditioner.argtypes = [vp, vp, vp, ip, vp]
@@ -222,6 +225,10 @@ class Problem:
         except Exception:
             pass
 
+    def set_kappa(self, kappa, stream=None):
+        """Replace kappa (device, N*N float64); call refresh() on every Stepper of this problem afterwards."""
+        _check(lib().irk_problem_set_kappa(self._h, _dev_ptr(kappa, self.N * self.N, "kappa"), _stream(stream)))
+
     def apply_mass(self, x, stream=None):
         y = _torch().empty_like(x)
         _check(lib().irk_apply_mass(self._h, _dev_ptr(x, self.n, "x"), _dev_ptr(y), _stream(stream)))
@@ -272,6 +279,10 @@ class Stepper:
             self.close()
         except Exception:
             pass
+
+    def refresh(self, stream=None):
+        """Rebuild the kappa-dependent multigrid state after Problem.set_kappa (buffers are reused)."""
+        _check(lib().irk_stepper_refresh(self._h, _stream(stream)))
 
     @property
     def levels(self) -> int:
@@ -390,30 +401,88 @@ class SolveConfig:
     options: dict = None
 
 
+def _solver_key(cfg: SolveConfig, device):
+    import numpy as np
+
+    tab = tuple(tuple(np.asarray(cfg.tableau[k], dtype=np.float64).ravel().tolist())
+                for k in ("A", "b", "c") if k in cfg.tableau)
+    opts = tuple(sorted((cfg.options or {}).items()))
+    return (int(cfg.N), str(device), float(cfg.dt), tab, opts)
+
+
+class _CachedSolver:
+    """A Problem/Stepper pair and the kappa it currently holds (version counts the loads of kappa)."""
+
+    def __init__(self, cfg: SolveConfig, kappa):
+        self.problem = Problem(cfg.N, kappa)
+        self.stepper = Stepper(self.problem, cfg.tableau, cfg.dt, **(cfg.options or {}))
+        self.kappa = kappa
+        self.version = 0
+
+    def hold(self, kappa):
+        """Load kappa (unless it is the one held) and refresh the stepper; returns the version holding it."""
+        if kappa is not self.kappa and not _torch().equal(kappa, self.kappa):
+            self.problem.set_kappa(kappa)
+            self.stepper.refresh()
+            self.version += 1
+        self.kappa = kappa
+        return self.version
+
+
+class _SolverCache:
+    """Solvers of IrkSolve, kept across calls with the same grid, tableau, dt, options and device: a call with
+    a new kappa reloads it into the cached problem and refreshes the stepper (no new workspace, no set-up of
+    the Krylov buffers). A backward pass whose kappa another call has replaced since its forward pass loads
+    its own again. Entries dropped from the cache live on while a pending backward pass holds them."""
+
+    def __init__(self, size: int = 2):
+        self.size = size
+        self.entries = {}  # key -> _CachedSolver; insertion order = age
+
+    def get(self, cfg: SolveConfig, kappa) -> _CachedSolver:
+        key = _solver_key(cfg, kappa.device)
+        e = self.entries.pop(key, None)
+        if e is None:
+            while len(self.entries) >= self.size:
+                self.entries.pop(next(iter(self.entries)))
+            e = _CachedSolver(cfg, kappa)
+        else:
+            e.hold(kappa)
+        self.entries[key] = e
+        return e
+
+    def clear(self):
+        self.entries.clear()
+
+
+_solver_cache = _SolverCache()
+
+
 def _make_irk_solve():
     torch = _torch()
 
     class IrkSolve(torch.autograd.Function):
-        """u_N = Phi(u_0, log kappa): nsteps implicit Runge-Kutta steps; backward = discrete adjoint."""
+        """u_N = Phi(u_0, log kappa): nsteps implicit Runge-Kutta steps; backward = discrete adjoint.
+        The Problem/Stepper of a configuration are cached across calls (see _SolverCache)."""
 
         @staticmethod
         def forward(ctx, u0, log_kappa, cfg: SolveConfig):
             kappa = torch.exp(log_kappa.detach()).contiguous()
-            prob = Problem(cfg.N, kappa)
-            stp = Stepper(prob, cfg.tableau, cfg.dt, **(cfg.options or {}))
+            e = _solver_cache.get(cfg, kappa)
             u = u0.detach().clone().contiguous()
-            stp.advance(u, cfg.nsteps)
-            ctx.stepper = stp
-            ctx.prob = prob
+            e.stepper.advance(u, cfg.nsteps)
+            ctx.solver = e
             ctx.cfg = cfg
-            ctx.save_for_backward(u0.detach().clone())
+            ctx.save_for_backward(u0.detach().clone(), kappa)
             return u
 
         @staticmethod
         def backward(ctx, grad_out):
-            (u0,) = ctx.saved_tensors
+            u0, kappa = ctx.saved_tensors
             cfg = ctx.cfg
-            lam0, grad, _ = ctx.stepper.adjoint(u0, cfg.nsteps, cfg.nsnap, grad_out.contiguous())
+            e = ctx.solver
+            e.hold(kappa)
+            lam0, grad, _ = e.stepper.adjoint(u0, cfg.nsteps, cfg.nsnap, grad_out.contiguous())
             return lam0, grad, None
 
     return IrkSolve

@@ -73,6 +73,7 @@ struct irk_problem {
   int dev = 0;  // device current at creation
   Geom g{};
   double* kappa = nullptr;  // padded element layout, FP64
+  int* bad = nullptr;       // device flag of the kappa check (create and irk_problem_set_kappa)
   // staging of irk_apply_mass / irk_apply_stiffness: two padded planes, allocated by the first such call
   mutable double* stage = nullptr;
   mutable std::mutex stage_mu;
@@ -161,6 +162,14 @@ struct irk_stepper {
   std::vector<hipGraphExec_t> graphs[2 + kMaxStages];
   bool dirk = false;  // stage-by-stage solves for a lower-triangular A (Section 2.3)
   int sys = -1;       // system the Krylov solver works on: -1 the coupled one, i >= 0 DIRK stage i
+  // adjoint workspace, allocated by the first irk_adjoint call: checkpoint planes (grown when a call needs
+  // more slots), the adjoint state, the padded gradient and two stage vectors
+  double* adj_snaps = nullptr;
+  int adj_slots = 0;
+  double* adj_lam = nullptr;
+  double* adj_grad = nullptr;
+  double* adj_nu = nullptr;
+  double* adj_kstep = nullptr;
 };
 
 namespace {
@@ -440,33 +449,34 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
     Level& lev = st->lv[l];
     lev.g = make_geom(sizes[l]);
     const long kcount = (long)lev.g.N * lev.g.pitch;
+    // buffers are allocated by the first call only (a refresh after a change of kappa reuses them)
     if (l == 0) {
       lev.kap64 = p->kappa;
     } else {
-      CHK(dev_alloc((void**)&lev.kap64, kcount * sizeof(double)));
+      if (!lev.kap64) CHK(dev_alloc((void**)&lev.kap64, kcount * sizeof(double)));
       lev.own64 = true;
       launch_coarsen_kappa(st->lv[l - 1].kap64, lev.kap64, st->lv[l - 1].g, lev.g, s);
     }
     if (st->prec == 0) {
       lev.kapc = lev.kap64;
     } else {
-      CHK(dev_alloc(&lev.kapc, kcount * sizeof(float)));
+      if (!lev.kapc) CHK(dev_alloc(&lev.kapc, kcount * sizeof(float)));
       launch_cast_f32(lev.kap64, (float*)lev.kapc, kcount, s);
     }
     const size_t pb = lev.g.plane * tsz;
     if (l >= 1) {
-      CHK(dev_alloc(&lev.t, pb));
-      CHK(dev_alloc(&lev.e, pb));
+      if (!lev.t) CHK(dev_alloc(&lev.t, pb));
+      if (!lev.e) CHK(dev_alloc(&lev.e, pb));
       HIPCHK(hipMemsetAsync(lev.t, 0, pb, s));
       HIPCHK(hipMemsetAsync(lev.e, 0, pb, s));
     }
     if (l < L - 1) {
-      CHK(dev_alloc(&lev.x, pb));
+      if (!lev.x) CHK(dev_alloc(&lev.x, pb));
       HIPCHK(hipMemsetAsync(lev.x, 0, pb, s));
     }
     if (l == 0 && L > 1) {
       const size_t tb = lev.g.plane * (st->prec == 0 ? sizeof(double) : sizeof(float));
-      CHK(dev_alloc(&lev.tp, tb));
+      if (!lev.tp) CHK(dev_alloc(&lev.tp, tb));
       HIPCHK(hipMemsetAsync(lev.tp, 0, tb, s));
     }
   }
@@ -504,17 +514,17 @@ int setup_multigrid(irk_stepper* st, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   for (int ey = 0; ey < lc.g.N; ++ey)
     for (int ex = 0; ex < lc.g.N; ++ex) kc[(size_t)ey * lc.g.N + ex] = kpad[(size_t)ey * lc.g.pitch + ex];
-  st->binv.assign(st->s, nullptr);
+  if (st->binv.empty()) st->binv.assign(st->s, nullptr);
   const int nc = (lc.g.N - 1) * (lc.g.N - 1);
   for (int i = 0; i < st->s; ++i) {
     std::vector<double> inv;
     CHK(coarse_inverse(kc, lc.g.N, st->dt * st->pd[i], inv));
     if (st->prec == 0) {
-      CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(double)));
+      if (!st->binv[i]) CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(double)));
       HIPCHK(hipMemcpy(st->binv[i], inv.data(), (size_t)nc * nc * sizeof(double), hipMemcpyHostToDevice));
     } else {
       std::vector<float> f(inv.begin(), inv.end());
-      CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(float)));
+      if (!st->binv[i]) CHK(dev_alloc(&st->binv[i], (size_t)nc * nc * sizeof(float)));
       HIPCHK(hipMemcpy(st->binv[i], f.data(), (size_t)nc * nc * sizeof(float), hipMemcpyHostToDevice));
     }
   }
@@ -563,22 +573,23 @@ int setup_mmg(irk_stepper* st, hipStream_t s) {
     Level& lev = st->ml[l];
     lev.g = make_geom(sizes[l]);
     const long kcount = (long)lev.g.N * lev.g.pitch;
+    // buffers are allocated by the first call only (a refresh after a change of kappa reuses them)
     if (l == 0) {
       lev.kap64 = p->kappa;
     } else {
-      CHK(dev_alloc((void**)&lev.kap64, kcount * sizeof(double)));
+      if (!lev.kap64) CHK(dev_alloc((void**)&lev.kap64, kcount * sizeof(double)));
       lev.own64 = true;
       launch_coarsen_kappa(st->ml[l - 1].kap64, lev.kap64, st->ml[l - 1].g, lev.g, s);
     }
     if (st->prec == 0) {
       lev.kapc = lev.kap64;
     } else {
-      CHK(dev_alloc(&lev.kapc, kcount * sizeof(float)));
+      if (!lev.kapc) CHK(dev_alloc(&lev.kapc, kcount * sizeof(float)));
       launch_cast_f32(lev.kap64, (float*)lev.kapc, kcount, s);
     }
     const size_t pb = (size_t)ns * lev.g.plane * tsz;
     auto zalloc = [&](void** q) -> int {
-      CHK(dev_alloc(q, pb));
+      if (!*q) CHK(dev_alloc(q, pb));
       HIPCHK(hipMemsetAsync(*q, 0, pb, s));
       return IRK_OK;
     };
@@ -668,11 +679,11 @@ int setup_mmg(irk_stepper* st, hipStream_t s) {
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) use[(size_t)i * n + j] = tr ? inv[(size_t)j * n + i] : inv[(size_t)i * n + j];
     if (st->prec == 0) {
-      CHK(dev_alloc(&st->mcinv[tr], use.size() * sizeof(double)));
+      if (!st->mcinv[tr]) CHK(dev_alloc(&st->mcinv[tr], use.size() * sizeof(double)));
       HIPCHK(hipMemcpy(st->mcinv[tr], use.data(), use.size() * sizeof(double), hipMemcpyHostToDevice));
     } else {
       std::vector<float> f(use.begin(), use.end());
-      CHK(dev_alloc(&st->mcinv[tr], f.size() * sizeof(float)));
+      if (!st->mcinv[tr]) CHK(dev_alloc(&st->mcinv[tr], f.size() * sizeof(float)));
       HIPCHK(hipMemcpy(st->mcinv[tr], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
     }
   }
@@ -1324,6 +1335,27 @@ int scratch_of_device(int dev, double** out) {
   return IRK_OK;
 }
 
+// Checks kappa (N * N element values, device) and, only if every value is finite and positive, packs it into the
+// problem's padded layout; waits for the stream (the check's verdict is read on the host).
+int load_kappa(irk_problem* p, const double* kappa, hipStream_t s) {
+  const int N = p->N;
+  int hbad = 0;
+  hipError_t e = hipMemsetAsync(p->bad, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    launch_check_kappa(kappa, N * N, p->bad, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, p->bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(IRK_EHIP, std::string("kappa check: ") + hipGetErrorString(e));
+  if (hbad) return fail(IRK_EINVAL, "kappa must be finite and positive everywhere");
+  launch_pack_elem(kappa, p->kappa, p->g, s);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(IRK_EHIP, std::string("kappa packing: ") + hipGetErrorString(e));
+  return IRK_OK;
+}
+
 int validate_stepper(const irk_stepper* st) {
   if (!st) return fail(IRK_EINVAL, "stepper is NULL");
   return IRK_OK;
@@ -1363,7 +1395,6 @@ int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stre
   *out = nullptr;
   if (N < 2 || N > 16384) return fail(IRK_EINVAL, "N must be in [2, 16384]");
   if (!kappa) return fail(IRK_EINVAL, "kappa is NULL");
-  hipStream_t s = S(stream);
   irk_problem* p = new irk_problem();
   p->N = N;
   p->g = make_geom(N);
@@ -1373,41 +1404,29 @@ int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stre
   }
   const long kc = (long)N * p->g.pitch;
   int rc = dev_alloc((void**)&p->kappa, kc * sizeof(double));
+  if (rc == IRK_OK) rc = dev_alloc((void**)&p->bad, sizeof(int));
+  if (rc == IRK_OK) rc = load_kappa(p, kappa, S(stream));
   if (rc != IRK_OK) {
-    delete p;
+    const std::string keep = g_err;
+    irk_problem_destroy(p);
+    g_err = keep;
     return rc;
-  }
-  int* bad = nullptr;
-  rc = dev_alloc((void**)&bad, sizeof(int));
-  if (rc != IRK_OK) {
-    irk_problem_destroy(p);
-    return rc;
-  }
-  int hbad = 0;
-  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
-  if (e == hipSuccess) {
-    launch_pack_elem(kappa, p->kappa, p->g, s);
-    launch_check_kappa(kappa, N * N, bad, s);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(bad);
-  if (e != hipSuccess) {
-    irk_problem_destroy(p);
-    return fail(IRK_EHIP, std::string("problem setup: ") + hipGetErrorString(e));
-  }
-  if (hbad) {
-    irk_problem_destroy(p);
-    return fail(IRK_EINVAL, "kappa must be finite and positive everywhere");
   }
   *out = p;
   return IRK_OK;
 }
 
+int irk_problem_set_kappa(irk_problem* p, const double* kappa, void* stream) {
+  g_err.clear();
+  if (!p || !p->kappa) return fail(IRK_EINVAL, "NULL problem");
+  if (!kappa) return fail(IRK_EINVAL, "kappa is NULL");
+  return load_kappa(p, kappa, S(stream));
+}
+
 void irk_problem_destroy(irk_problem* p) {
   if (!p) return;
   dev_free(p->kappa);
+  dev_free(p->bad);
   dev_free(p->stage);
   delete p;
 }
@@ -1474,6 +1493,11 @@ void irk_stepper_destroy(irk_stepper* st) {
   dev_free(st->dflag);
   dev_free(st->rw.partial);
   dev_free(st->rw.counter);
+  dev_free(st->adj_snaps);
+  dev_free(st->adj_lam);
+  dev_free(st->adj_grad);
+  dev_free(st->adj_nu);
+  dev_free(st->adj_kstep);
   for (auto& v : st->graphs)
     for (hipGraphExec_t g : v)
       if (g) (void)hipGraphExecDestroy(g);
@@ -1668,6 +1692,26 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   return IRK_OK;
 }
 
+int irk_stepper_refresh(irk_stepper* st, void* stream) {
+  g_err.clear();
+  CHK(validate_stepper(st));
+  hipStream_t hs = S(stream);
+  // nothing of the stepper may still run while its kappa-dependent state is rebuilt
+  HIPCHK(hipStreamSynchronize(hs));
+  // the captured Arnoldi graphs hold the old Chebyshev coefficients as kernel arguments: capture again
+  for (auto& v : st->graphs) {
+    for (hipGraphExec_t g : v)
+      if (g) (void)hipGraphExecDestroy(g);
+    v.clear();
+  }
+  st->have_prev = false;
+  for (int& it : st->last_its) it = 0;
+  int rc = setup_multigrid(st, hs);
+  if (rc == IRK_OK && st->opt.precond == IRK_PC_MONOLITHIC) rc = setup_mmg(st, hs);
+  if (rc == IRK_OK && hipStreamSynchronize(hs) != hipSuccess) rc = fail(IRK_EHIP, "refresh synchronisation failed");
+  return rc;
+}
+
 int irk_stepper_sizes(const irk_stepper* st, int* N, int* s, int* levels) {
   CHK(validate_stepper(st));
   if (N) *N = st->prob->N;
@@ -1823,28 +1867,26 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
   hipStream_t s = S(stream);
   const Geom& g = st->g;
   const int slots = std::min(nsnap, std::max(nsteps, 1));
-  double* snaps = nullptr;
-  double* lam = nullptr;
-  double* grad = nullptr;
-  double* nu = nullptr;
-  double* kstep = nullptr;
   const long gcount = (long)g.N * g.pitch;
-  int rc = dev_alloc((void**)&snaps, (size_t)slots * g.plane * sizeof(double));
-  if (rc == IRK_OK) rc = dev_alloc((void**)&lam, g.plane * sizeof(double));
-  if (rc == IRK_OK) rc = dev_alloc((void**)&grad, gcount * sizeof(double));
-  if (rc == IRK_OK) rc = dev_alloc((void**)&nu, st->vlen * sizeof(double));
-  if (rc == IRK_OK) rc = dev_alloc((void**)&kstep, st->vlen * sizeof(double));
-  auto cleanup = [&]() {
-    dev_free(snaps);
-    dev_free(lam);
-    dev_free(grad);
-    dev_free(nu);
-    dev_free(kstep);
-  };
-  if (rc != IRK_OK) {
-    cleanup();
-    return rc;
+  // the stepper's workspace: allocated by the first call, the checkpoint planes grown when more slots are needed
+  int rc = IRK_OK;
+  if (slots > st->adj_slots) {
+    // every earlier call waited for its own work before returning, so the old planes are idle
+    dev_free(st->adj_snaps);
+    st->adj_snaps = nullptr;
+    st->adj_slots = 0;
+    CHK(dev_alloc((void**)&st->adj_snaps, (size_t)slots * g.plane * sizeof(double)));
+    st->adj_slots = slots;
   }
+  if (!st->adj_lam) CHK(dev_alloc((void**)&st->adj_lam, g.plane * sizeof(double)));
+  if (!st->adj_grad) CHK(dev_alloc((void**)&st->adj_grad, gcount * sizeof(double)));
+  if (!st->adj_nu) CHK(dev_alloc((void**)&st->adj_nu, st->vlen * sizeof(double)));
+  if (!st->adj_kstep) CHK(dev_alloc((void**)&st->adj_kstep, st->vlen * sizeof(double)));
+  double* snaps = st->adj_snaps;
+  double* lam = st->adj_lam;
+  double* grad = st->adj_grad;
+  double* nu = st->adj_nu;
+  double* kstep = st->adj_kstep;
   if (hipMemsetAsync(grad, 0, gcount * sizeof(double), s) != hipSuccess) rc = fail(IRK_EHIP, "memset");
   launch_pack(u0, st->u, g, 1, s);
   launch_pack(lambda_T, lam, g, 1, s);
@@ -1911,7 +1953,6 @@ int irk_adjoint(irk_stepper* st, const double* u0, int nsteps, int nsnap, const 
     stats->steps_done = done;
     if (rc != IRK_OK) stats->failed_step = nsteps - 1 - done;
   }
-  cleanup();
   return rc;
 }
 
