@@ -59,6 +59,31 @@ __device__ __forceinline__ W9<TC> stencil_weights(TC kSW, TC kSE, TC kNW, TC kNE
   return q;
 }
 
+// A value from the adjacent lane of the wavefront (DPP wavefront shift by one lane: kDppFromLower gives lane l the
+// value of lane l - 1, kDppFromUpper that of lane l + 1; the lane without a source gets 0)
+constexpr int kDppFromLower = 0x138, kDppFromUpper = 0x130;
+template <typename TC, int CTRL>
+__device__ __forceinline__ TC lane_shift(TC v);
+template <>
+__device__ __forceinline__ float lane_shift<float, kDppFromLower>(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kDppFromLower, 0xF, 0xF, false));
+}
+template <>
+__device__ __forceinline__ float lane_shift<float, kDppFromUpper>(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kDppFromUpper, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <>
+__device__ __forceinline__ double lane_shift<double, kDppFromLower>(double v) { return lane_shift_f64<kDppFromLower>(v); }
+template <>
+__device__ __forceinline__ double lane_shift<double, kDppFromUpper>(double v) { return lane_shift_f64<kDppFromUpper>(v); }
+
 // LDS plane of the region with one spare row above and below and one spare word before and after, so that every
 // neighbour address of a region node is inside the array (the spare words are zeroed once per launch)
 template <int RY>
@@ -268,19 +293,30 @@ __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ 
     }
     bx[r] = in[r] ? tv[r] - bx[r] : (TC)0;
   }
-  store_rows<TC, RY, RW>(nxt, l, r0, bx);
-  __syncthreads();
-  // full-weighting restriction (P^T of bilinear interpolation) to the coarse nodes of the tile
+  // full-weighting restriction (P^T of bilinear interpolation) to the coarse nodes of the tile. The wavefront spans
+  // the region's 64 columns, so each lane's row neighbours come from the adjacent lanes by wavefront shifts (no LDS
+  // reads at stride 2, which would put two lanes on each bank); the coarse columns' row sums go to a compact plane
+  // (row stride CS, rows two apart half the banks apart) in the buffer of the previous iterate, free now, and each
+  // half-wavefront then weights three rows of that plane for one coarse row.
   {
-    constexpr int CX = TX / 2, CY = TY / 2;
+    constexpr int CX = TX / 2, CY = TY / 2, CS = 48;
+    static_assert(CX <= 32 && RY * CS <= PL::SIZE, "compact restriction plane");
     const int I0 = (i0 + 1) / 2, J0 = (j0 + 1) / 2;
-    for (int idx = threadIdx.x; idx < CX * CY; idx += NW * WL) {
-      const int I = I0 + idx % CX, J = J0 + idx / CX;
-      if (I > gc.N - 1 || J > gc.N - 1) continue;
-      const TC* R = nxt + PL::at(2 * J - oy, 2 * I - ox);
-      const TC v = R[0] + (TC)0.5 * (R[1] + R[-1] + R[WL] + R[-WL]) +
-                   (TC)0.25 * (R[WL + 1] + R[WL - 1] + R[-WL + 1] + R[-WL - 1]);
-      st(tc + (unsigned)J * gc.pitch + I, v);
+    const int c0 = 2 * I0 - ox;  // local column of the tile's first coarse column
+    const bool ccol = l >= c0 && l < c0 + 2 * CX && ((l - c0) & 1) == 0;
+    const int cc = (l - c0) >> 1;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const TC left = lane_shift<TC, kDppFromLower>(bx[r]), right = lane_shift<TC, kDppFromUpper>(bx[r]);
+      if (ccol) nxt[(r0 + r) * CS + cc] = bx[r] + (TC)0.5 * (left + right);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 32 * CY; k += NW * WL) {
+      const int kc = k & 31, cj = k >> 5;
+      const int I = I0 + kc, J = J0 + cj;
+      if (kc >= CX || I > gc.N - 1 || J > gc.N - 1) continue;
+      const TC* hrow = nxt + (2 * J - oy) * CS + kc;
+      st(tc + (unsigned)J * gc.pitch + I, hrow[0] + (TC)0.5 * (hrow[-CS] + hrow[CS]));
     }
   }
 }
