@@ -59,6 +59,17 @@ __device__ __forceinline__ W9<TC> stencil_weights(TC kSW, TC kSE, TC kNW, TC kNE
   return q;
 }
 
+// Keeps the weights' computation ahead of the next barrier: left alone, the compiler sinks it to the first use
+// after the barrier, where it can no longer overlap the global loads still in flight (an empty statement that
+// only reads the values; it emits no instruction).
+template <typename TC, int RW>
+__device__ __forceinline__ void weights_ready(const W9<TC> (&w)[RW]) {
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+    asm volatile("" ::"v"(w[r].c), "v"(w[r].e), "v"(w[r].w), "v"(w[r].n), "v"(w[r].s), "v"(w[r].ne), "v"(w[r].nw),
+                 "v"(w[r].se), "v"(w[r].sw), "v"(w[r].dinv));
+}
+
 // A value from the adjacent lane of the wavefront (DPP wavefront shift by one lane: kDppFromLower gives lane l the
 // value of lane l - 1, kDppFromUpper that of lane l + 1; the lane without a source gets 0)
 constexpr int kDppFromLower = 0x138, kDppFromUpper = 0x130;
@@ -212,16 +223,18 @@ __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ 
   bool in[RW];
   unsigned p[RW];
   TC tv[RW], kw[RW + 1], ke[RW + 1], wv[RW];
+  // diffusivities first: the stencil weights are formed while the right-hand side's loads are still in flight
+  load_kappa_cols<TC, RW>(kap, i, jf, g, kw, ke);
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, N);
     p[r] = in[r] ? (unsigned)(jf + r) * g.pitch + i : 0;
     tv[r] = ld<TC>(t + p[r]);
   }
-  load_kappa_cols<TC, RW>(kap, i, jf, g, kw, ke);
   if (COUPLE) {
     // w = sum_q a_q z_q in FP64; the stage loop is unrolled over its bound with a uniform guard, so the loads of
-    // all rows of a stage plane are in flight together
+    // all rows of a stage plane are in flight together (loading two planes ahead of the guard would take the
+    // kernel past 64 registers, half the occupancy)
     double acc[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) acc[r] = 0.0;
@@ -239,18 +252,26 @@ __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ 
 #pragma unroll
     for (int r = 0; r < RW; ++r) wv[r] = in[r] ? (TC)acc[r] : (TC)0;
   }
+  // the stencil weights need only the diffusivities, loaded first: without coupling they are formed while the
+  // right-hand side's loads are in flight; with it, after the coupling (earlier, the kernel would need more than
+  // 64 registers, half the occupancy)
+  W9<TC> w[RW];
+  if constexpr (!COUPLE) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+    weights_ready<TC, RW>(w);
+  }
   zero_spare<TC, RY>(sA);
   zero_spare<TC, RY>(sB);
 #pragma unroll
   for (int r = 0; r < RW; ++r) tv[r] = in[r] ? tv[r] * ts : (TC)0;
-  if (COUPLE) {
+  if constexpr (COUPLE) {
     store_rows<TC, RY, RW>(sB, l, r0, wv);
     __syncthreads();
     couple_rows<TC, RY, RW>(sB, l, r0, wv, kw, ke, cp, tv);
-  }
-  W9<TC> w[RW];
 #pragma unroll
-  for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+    for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+  }
   // first Chebyshev step from x0 = 0 is pointwise: x1 = c0 D^{-1} t
   TC xc[RW], xp[RW], bx[RW];
   {
@@ -345,6 +366,8 @@ __global__ __launch_bounds__(NW* WL) void mg_up_kernel(const TT* __restrict__ t,
 
   bool in[RW];
   TC tv[RW], xc[RW], xp[RW], bx[RW], kw[RW + 1], ke[RW + 1];
+  // diffusivities first: the stencil weights are formed while the iterate's loads are still in flight
+  load_kappa_cols<TC, RW>(kap, i, jf, g, kw, ke);
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, N);
@@ -355,13 +378,13 @@ __global__ __launch_bounds__(NW* WL) void mg_up_kernel(const TT* __restrict__ t,
     tv[r] = in[r] ? a : (TC)0;
     xp[r] = in[r] ? b : (TC)0;
   }
-  load_kappa_cols<TC, RW>(kap, i, jf, g, kw, ke);
-  zero_spare<TC, RY>(sA);
-  zero_spare<TC, RY>(sB);
-  store_rows<TC, RY, RW>(sA, l, r0, xp);
   W9<TC> w[RW];
 #pragma unroll
   for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+  weights_ready<TC, RW>(w);
+  zero_spare<TC, RY>(sA);
+  zero_spare<TC, RY>(sB);
+  store_rows<TC, RY, RW>(sA, l, r0, xp);
   __syncthreads();
   // first step from the corrected x0: x1 = x0 + c0 D^{-1} (t - B x0)
   apply_b<TC, RY, RW>(sA, l, r0, w, xp, bx);
@@ -597,22 +620,24 @@ __global__ __launch_bounds__(NW* WL) void mg_down3_kernel(const TS* __restrict__
   bool in[RW];
   unsigned p[RW];
   TC tv[RW], kw[RW + 1], ke[RW + 1];
+  // A's diffusivities first: its stencil weights are formed while the right-hand side's loads are in flight
+  load_kappa_cols<TC, RW>(kA, i, jf, gA, kw, ke);
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     in[r] = interior(i, jf + r, gA.N);
     p[r] = in[r] ? (unsigned)(jf + r) * gA.pitch + i : 0;
     tv[r] = ld<TC>(tA + p[r]);
   }
-  load_kappa_cols<TC, RW>(kA, i, jf, gA, kw, ke);
+  W9<TC> w[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
+  weights_ready<TC, RW>(w);
   flat_kappa<TC, RB, RB, NT>(sKB, kB, oBx, oBy, gB);
   flat_kappa<TC, RC, RC, NT>(sKC, kC, oCx, oCy, gC);
   zero_spare<TC, RY>(sA);
   zero_spare<TC, RY>(sA2);
 #pragma unroll
   for (int r = 0; r < RW; ++r) tv[r] = in[r] ? tv[r] : (TC)0;
-  W9<TC> w[RW];
-#pragma unroll
-  for (int r = 0; r < RW; ++r) w[r] = stencil_weights<TC>(kw[r], ke[r], kw[r + 1], ke[r + 1], m, alpha);
   TC xc[RW], xp[RW], bx[RW];
   {
     const TC c0 = (TC)cA.c0;
