@@ -126,7 +126,9 @@ void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, 
 void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
                            const Coefs& a, double dt, hipStream_t st, bool ia = false);
 // f_i = -K u + F (F may be null), i = 0..s-1
-void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st);
+// f (and f2 if not NULL: a second copy) = -K u + F in every stage plane
+void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st,
+                      double* f2 = nullptr);
 // y = M x or y = K x
 void launch_mass(const double* x, double* y, Geom g, hipStream_t st);
 void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipStream_t st);
@@ -213,6 +215,7 @@ struct OrthoArgs {
   double* w;             // vector updated in place when coef != nullptr
   long len;              // values per vector
   const double* coef;    // if set: w -= coef_sign * sum_k coef[k]*vscale[k]*V_k first
+  int assign;            // with coef: w = -coef_sign * sum_k ... (w is not read: it may hold anything)
   double coef_sign;
   const double* vscale;  // per-vector scale (nullptr = 1)
   int want_dots;         // compute dots[k] = vscale[k] * V_k . w (after the update)

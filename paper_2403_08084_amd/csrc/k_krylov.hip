@@ -63,7 +63,7 @@ __device__ __forceinline__ void process(const OrthoArgs& a, const double (&c)[NV
   double wv[U];
   double v[U][NVV];
 #pragma unroll
-  for (int u = 0; u < U; ++u) wv[u] = a.w[q0 + u * stride];
+  for (int u = 0; u < U; ++u) wv[u] = (AX && a.assign) ? 0.0 : a.w[q0 + u * stride];
   if (NEEDV) {
 #pragma unroll
     for (int u = 0; u < U; ++u)

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BX* SBY) void stage_operator_kernel(const double* _
 
 __global__ __launch_bounds__(BX* BY) void stage_rhs_kernel(const double* __restrict__ u, const double* __restrict__ F,
                                                            double* __restrict__ f, const double* __restrict__ kap,
-                                                           Geom g, int s) {
+                                                           Geom g, int s, double* __restrict__ f2) {
   int i, j;
   if (!node_of_thread(g, i, j)) return;
   const int P = g.pitch;
@@ -239,6 +239,8 @@ __global__ __launch_bounds__(BX* BY) void stage_rhs_kernel(const double* __restr
   double v = -stiff(load_nb(u, p, P), load_kap(kap, p, P));
   if (F) v += F[p];
   for (int r = 0; r < s; ++r) f[r * g.plane + p] = v;
+  if (f2)
+    for (int r = 0; r < s; ++r) f2[r * g.plane + p] = v;
 }
 
 __global__ __launch_bounds__(BX* BY) void mass_kernel(const double* __restrict__ x, double* __restrict__ y, Geom g) {
@@ -433,8 +435,9 @@ void launch_stage_operator(const double* x, double* y, const double* f, const do
   else
     stage_operator_t<false>(x, y, f, kappa, g, s, a, dt, st);
 }
-void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st) {
-  launch_k(stage_rhs_kernel, stencil_grid(g), dim3(BX, BY), st, u, F, f, kappa, g, s);
+void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st,
+                      double* f2) {
+  launch_k(stage_rhs_kernel, stencil_grid(g), dim3(BX, BY), st, u, F, f, kappa, g, s, f2);
 }
 void launch_mass(const double* x, double* y, Geom g, hipStream_t st) {
   launch_k(mass_kernel, stencil_grid(g), dim3(BX, BY), st, x, y, g);

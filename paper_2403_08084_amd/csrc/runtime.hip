@@ -161,6 +161,9 @@ struct irk_stepper {
   // [2 + i] the single-stage system of DIRK stage i
   std::vector<hipGraphExec_t> graphs[2 + kMaxStages];
   bool dirk = false;  // stage-by-stage solves for a lower-triangular A (Section 2.3)
+  // set by the time step when its right-hand side kernel also wrote f into V_0: the next DCGS2 solve of st->f
+  // without a guess then needs no copy (cleared by every solve)
+  bool v0_is_f = false;
   int sys = -1;       // system the Krylov solver works on: -1 the coupled one, i >= 0 DIRK stage i
   // adjoint workspace, allocated by the first irk_adjoint call: checkpoint planes (grown when a call needs
   // more slots), the adjoint state, the padded gradient and two stage vectors
@@ -948,7 +951,7 @@ struct SolveInfo {
 // re-orthogonalisation coefficients and its subdiagonal entry becomes that direction's exact norm
 // (the provisional entry is the norm predicted from the reduction of step j).
 int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s,
-                 double* x) {
+                 double* x, bool v0_is_f) {
   const int m = st->opt.restart;
   const long n = sys_len(st);
   double* h = st->hres;
@@ -963,11 +966,12 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
   // |f| and the initial residual r_0 = V_0 (= f without a guess). Step 0 needs neither norm on the host
   // (it normalises u_0 from its own reduction), so it is queued before the host waits for them.
   CHK(norm2(st, f, n, res_slot(st, 0), nullptr, s));
+  // without a guess x is not cleared: the first cycle's solution update assigns x = Z y (x_unset)
+  bool x_unset = !use_guess;
   if (use_guess) {
     CHK(apply_op(st, x, st->V, f, trans, s));
     CHK(norm2(st, st->V, n, res_slot(st, 0) + 1, nullptr, s));
-  } else {
-    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  } else if (!v0_is_f) {
     HIPCHK(hipMemcpyAsync(st->V, f, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   HIPCHK(hipMemcpyAsync(h, res_slot(st, 0), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -991,6 +995,7 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
   double beta = use_guess ? std::sqrt(h[1]) : fnorm;
   const double target = st->opt.rtol * fnorm;
   if (beta <= target) {
+    if (x_unset) HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
     info.rel = beta / fnorm;
     info.discarded = step0_queued ? (two ? 2 : 1) : 0;
     st->last_its[key] = 0;
@@ -1072,8 +1077,14 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
       ax.len = n;
       ax.coef = ycoef_dev(st);
       ax.coef_sign = -1.0;
+      ax.assign = x_unset ? 1 : 0;
       ax.result = res_slot(st, 3);
       CHK(ortho(st, ax, s));
+      x_unset = false;
+    }
+    if (x_unset) {
+      HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+      x_unset = false;
     }
     CHK(apply_op(st, x, st->V, f, trans, s));
     CHK(norm2(st, st->V, n, res_slot(st, 0), nullptr, s));
@@ -1099,7 +1110,9 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
 int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s,
            double* x = nullptr) {
   if (!x) x = st->k;
-  if (st->opt.orth == IRK_ORTH_DCGS2) return fgmres_dcgs2(st, f, trans, use_guess, info, s, x);
+  const bool v0_is_f = st->v0_is_f && f == st->f;
+  st->v0_is_f = false;
+  if (st->opt.orth == IRK_ORTH_DCGS2) return fgmres_dcgs2(st, f, trans, use_guess, info, s, x, v0_is_f);
   const int m = st->opt.restart;
   const long n = sys_len(st);
   double* sig = sigma_dev(st);
@@ -1276,9 +1289,12 @@ void init_stats(irk_stats* stats) {
 // one forward step on st->u (padded); stage derivatives left in st->k
 int forward_step(irk_stepper* st, const double* Fp, SolveInfo& si, hipStream_t s) {
   const double n = nodes(st->g), rb = n * (16.0 + (Fp ? 8.0 : 0.0) + 8.0 * st->s), ub = n * (8.0 * st->s + 16.0);
-  CHK(timer_arm(st, IRK_KFAM_OTHER, rb, rb));
-  launch_stage_rhs(st->u, Fp, st->f, st->prob->kappa, st->g, st->s, s);
   const bool guess = st->opt.initial_guess == IRK_GUESS_PREV && st->have_prev;
+  // the coupled DCGS2 solve without a guess starts from V_0 = f: the kernel writes that copy too
+  const bool f_to_v0 = !guess && !st->dirk && st->opt.orth == IRK_ORTH_DCGS2;
+  CHK(timer_arm(st, IRK_KFAM_OTHER, rb + (f_to_v0 ? n * 8.0 * st->s : 0.0), rb + (f_to_v0 ? n * 8.0 * st->s : 0.0)));
+  launch_stage_rhs(st->u, Fp, st->f, st->prob->kappa, st->g, st->s, s, f_to_v0 ? st->V : nullptr);
+  st->v0_is_f = f_to_v0;
   CHK(stage_solve(st, st->f, false, guess, si, s));
   st->have_prev = true;
   CHK(timer_arm(st, IRK_KFAM_OTHER, ub, ub));
