@@ -155,9 +155,13 @@ def rel_errors(states, ref):
 
 
 def sources_sha16():
-    """sha256 prefix over the HIP sources (a counter summary is used only while the kernels are unchanged)."""
+    """sha256 prefix over the library's sources: the files the build compiles and the headers they include (a
+    counter summary is used only while the kernels are unchanged)."""
+    from paper_2403_08084_amd import build as libbuild
+
+    names = sorted(set(libbuild.SOURCES) | {n for n in os.listdir(CSRC) if n.endswith(".h")})
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in names:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
