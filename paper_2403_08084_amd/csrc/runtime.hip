@@ -327,12 +327,12 @@ Bytes mmg_up_bytes(const irk_stepper* st, int l) {
 int arm(irk_stepper* st, int family, const Bytes& b) { return timer_arm(st, family, b.model, b.min); }
 
 // Algorithmic bytes of one streaming Gram-Schmidt pass over s*n interior values:
-// the basis vectors it reads, w read, and w written when it updates w.
+// the basis vectors it reads, w read (not when the pass assigns w), and w written when it updates w.
 double ortho_bytes(const irk_stepper* st, const OrthoArgs& a) {
   const double vec = 8.0 * (double)(a.len / st->g.plane) * (double)(st->prob->N - 1) * (st->prob->N - 1);
   const bool ax = a.coef != nullptr, dt = a.want_dots != 0;
   const int nvec = (a.nv > 0 && (ax || dt)) ? a.nv : 0;
-  return vec * (nvec + 1 + (ax ? 1 : 0));
+  return vec * (nvec + ((ax && a.assign) ? 0 : 1) + (ax ? 1 : 0));
 }
 
 // Algorithmic bytes of the two DCGS2 passes over nv finished vectors: the reduction reads Q, u and w;
