@@ -176,18 +176,23 @@ def test_dirk_gs_lower_with_exact_blocks_converges_in_one_iteration():
     N, dt = 8, 1e-2
     kap = synth.grf_kappa(N, 3)
     f = synth.random_stage_block(N, 3, 2).ravel()
+    sols = {}
     for orth, its in ((P.ORTH_CGS2, 1), (P.ORTH_DCGS2, 2)):
         _, stp = make(N, kap, P.tableaux.alexander(), dt, precond=P.PC_GS_LOWER, rtol=1e-12, orth=orth)
         assert stp.levels == 1
-        _, stats = stp.solve_stages(dev(f))
+        k, stats = stp.solve_stages(dev(f))
         assert 1 <= stats["fgmres_its_total"] <= its
         # the transposed system is preconditioned by the transpose of P_L, exact here as well
-        _, stats = stp.solve_stages(dev(f), transpose=True)
+        kt, stats = stp.solve_stages(dev(f), transpose=True)
         assert 1 <= stats["fgmres_its_total"] <= its
+        sols[orth] = (host(k), host(kt))
         # s = 1 (backward Euler) with P_D likewise
         _, stp1 = make(N, kap, P.tableaux.radau_iia(1), dt, precond=P.PC_JACOBI, rtol=1e-12, orth=orth)
         _, stats = stp1.solve_stages(dev(f[: (N - 1) ** 2]))
         assert 1 <= stats["fgmres_its_total"] <= its
+    # whatever step notices it, both processes return the exact solve (forward and transposed)
+    for a, b in zip(sols[P.ORTH_CGS2], sols[P.ORTH_DCGS2]):
+        assert rel(b, a) < 1e-11
 
 
 def test_iterations_grow_with_stages_and_gs_beats_jacobi():
