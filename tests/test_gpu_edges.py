@@ -82,3 +82,31 @@ def test_empty_work():
     assert rc == 0 and st["steps_done"] == 0 and np.array_equal(host(u), u0)
     x, st = stp.solve_stages(dev(np.zeros(3 * (N - 1) ** 2)))
     assert not np.any(host(x)) and st["fgmres_its_total"] == 0
+
+
+def test_device_allocation_failure_reported_and_freed():
+    # N = 16384 (the largest grid the library accepts), s = 3, restart 32: one stage vector is 3 (N+1) * pitch
+    # doubles = 6.45 GB, so the Krylov basis V (33 vectors, 213 GB) fits in the 288 GB of HBM and the flexible
+    # basis Z (32 vectors, 206 GB) after it cannot: creation must stop at Z with IRK_ENOMEM and free V again
+    import torch
+
+    N = 16384
+    kap = torch.ones(N * N, dtype=torch.float64, device="cuda")
+    prob = P.Problem(N, kap)
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    assert total < 420e9  # V and Z together exceed the device
+    with pytest.raises(P.IrkError) as e:
+        P.Stepper(prob, P.tableaux.radau_iia(3), 1e-3, restart=32)
+    assert e.value.code == P.IRK_ENOMEM and "hipMalloc" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (256 << 20)
+    prob.close()
+    del kap
+    # the library is usable afterwards
+    n = 16
+    _, stp = make(n, np.ones(n * n), P.tableaux.radau_iia(3), 1e-3, rtol=1e-12)
+    u0, amps = synth.sine_modes_u0(n, 0)
+    u = dev(u0)
+    stp.advance(u, 1)
+    assert rel(host(u), step.closed_form_modes(n, OT.radau_iia(3), 1e-3, 1, amps)[1]) < 1e-10

@@ -4,7 +4,8 @@ Configs 3/4 (1024^2, variable kappa) are compared node by node with the oracle's
 (oracle.step.DecoupledLU: the full coupled LU does not fit at 1024^2; the decoupled tier equals it to rounding,
 pinned at smaller sizes), computed once per session: the relative L2 error of the whole interior vector at every
 one of the 20 steps, maximised over the steps. Config 2 (512^2, kappa = 1) is compared with the closed form at
-every step; config 5 (512^2 adjoint) with the oracle gradient stored by tests/golden/make_golden.py and with
+every step; config 5 (512^2 adjoint) with the oracle's whole gradient and lam_0 (decoupled direct tier, computed
+once per session), with the summary of its coupled-LU gradient stored by tests/golden/make_golden.py and with
 central finite differences."""
 import json
 import os
@@ -85,9 +86,30 @@ def test_config2_fullsize_closed_form():
     assert worst < 1e-10, worst
 
 
+def _oracle_adjoint(N, dt, nsteps):
+    """The oracle's gradient of config 5's objective from its eigen-decoupled direct tier (forward, target and
+    transposed solves; about a minute on the host): (J, lam_0, grad)."""
+    from oracle import adjoint
+
+    key = ("adjoint", N, dt, nsteps)
+    if key not in _ORACLE:
+        tab = OT.radau_iia(3)
+        kap = synth.grf_kappa(N, 1)
+        u0, _ = synth.sine_modes_u0(N, 0)
+        t0 = time.time()
+        ustar = step.run(N, synth.grf_kappa(N, 2), tab, dt, nsteps, u0, tier="decoupled")[-1]
+        fwd = adjoint.forward(N, kap, tab, dt, nsteps, u0, tier="decoupled")
+        J, lamN = adjoint.objective(fwd[2], fwd[0][-1], ustar)
+        lam0, grad = adjoint.gradient(N, kap, tab, dt, nsteps, u0, lamN, tier="decoupled", fwd=fwd)
+        print(f"oracle adjoint {N}^2 {nsteps} steps: {time.time() - t0:.1f} s", flush=True)
+        _ORACLE[key] = (J, lam0, grad)
+    return _ORACLE[key]
+
+
 def test_config5_fullsize_adjoint():
-    """Adjoint gradient at 512^2, 40 steps, 8 snapshots: against the oracle gradient (1e-8 relative) and central
-    finite differences.
+    """Adjoint gradient at 512^2, 40 steps, 8 snapshots: the whole gradient and lam_0 against the oracle's
+    (decoupled direct tier, 1e-8 relative L2), against the stored summary of the oracle's coupled-LU gradient
+    written by tests/golden/make_golden.py, and against central finite differences.
 
     FD noise: J = 0.025 while |grad.d| ~ 6e-7 for a seeded unit direction d (the gradient is spread over 262,144
     elements), so J(theta +- h d) differ by ~1e-10 at h = 1e-4. Forward solves at rtol 2e-13 (the attainable
@@ -121,6 +143,10 @@ def test_config5_fullsize_adjoint():
     lam0, grad, st = stp.adjoint(dev(u0), nsteps, 8, lamN)
     assert st["forward_advances"] == 70  # optimal binomial schedule, 40 steps with 8 snapshots
     gh = host(grad)
+    Jo, lam0o, grado = _oracle_adjoint(N, dt, nsteps)
+    eg, el = rel(gh, grado), rel(host(lam0), lam0o)
+    print(f"config 5: J {J0:.15e} (oracle {Jo:.15e}), gradient rel L2 {eg:.2e}, lam_0 rel L2 {el:.2e}")
+    assert abs(J0 - Jo) < 1e-9 * abs(Jo) and eg < 1e-8 and el < 1e-8
     idx = np.asarray(g["grad_indices"])
     G = synth.sketch_vectors(N * N, g["n_sketch"], g["sketch_seed"])
     assert _compare(gh, g["grad"], idx, G) < 1e-8
