@@ -56,7 +56,9 @@ typedef enum {
   IRK_ENOMEM = -2,      /* device or host allocation failed                    */
   IRK_EHIP = -3,        /* a HIP runtime call failed                           */
   IRK_ENOCONV = -4,     /* FGMRES missed rtol within max_it                    */
-  IRK_EBREAKDOWN = -5   /* non-finite value met inside the Krylov iteration    */
+  IRK_EBREAKDOWN = -5   /* non-finite value met inside the Krylov iteration
+                           (the stepper clears its work vectors and stays
+                           usable)                                             */
 } irk_status;
 
 /* eq:pcbjac, eq:pcbgs, eq:pcranald, the block upper-triangular variant of eq:pcbgs (Section 3.1),
@@ -239,8 +241,8 @@ int irk_solve_stages(irk_stepper *st, const double *f, double *k, int transpose,
 
 /* a1+a5+a6: advance u (device n, in/out) by nsteps time steps of size dt with forcing F
  * (device n or NULL), u^{n+1} = u^n + dt * sum_i b_i k_i (IA: dt * sum_i (A^{-T} b)_i w_i).
- * On IRK_ENOCONV u holds the last step that converged and stats->failed_step names the
- * failing step. Synchronises. */
+ * On IRK_ENOCONV or IRK_EBREAKDOWN u holds the last step that converged and stats->failed_step
+ * names the failing step. Synchronises. */
 int irk_advance(irk_stepper *st, double *u, const double *F, int nsteps, irk_stats *stats, void *stream);
 
 /* a8+a9: discrete adjoint of nsteps steps from u0 (device n) with F = 0. Given

@@ -129,7 +129,6 @@ struct irk_stepper {
   double* Z = nullptr;    // m vectors
   double* f = nullptr;    // right-hand side (s planes)
   double* k = nullptr;    // solution (s planes)
-  double* kprev = nullptr;
   double* tmp = nullptr;  // s planes
   double* tmp2 = nullptr; // s planes
   double* u = nullptr;    // state plane
@@ -1247,7 +1246,55 @@ void add_stats(irk_stats* stats, const SolveInfo& si) {
 // Solve the stage system (I (x) M + dt A (x) K) k = f (A^T if trans) into st->k: one FGMRES on the coupled
 // system, or, for a DIRK stepper, block substitution with one single-stage FGMRES per stage (Section 2.3):
 // (M + dt a_ii K) k_i = f_i - dt K sum_{j<i} a_ij k_j (transposed: backwards, j > i with a_ji).
+// The interior-only kernels (stage operator, stage right-hand side, multigrid levels) rely on every padded plane
+// holding zeros in its boundary ring and padding. The flat vector kernels (Arnoldi updates, solution update) write
+// those entries as 0 * c, which stays zero only while every coefficient c is finite. After a breakdown on
+// non-finite data (including Arnoldi steps queued ahead of the host's check), the work planes are cleared to the
+// state set-up left, so the stepper's next solve is unaffected. The state plane u is left alone (it holds the
+// last good state the caller gets back).
+int clear_work(irk_stepper* st, hipStream_t s) {
+  const size_t vb = st->vlen * sizeof(double);
+  const size_t tb = (size_t)std::max(st->s, 2) * st->g.plane * sizeof(double);
+  auto clr = [&](void* q, size_t bytes) -> int {
+    if (q) HIPCHK(hipMemsetAsync(q, 0, bytes, s));
+    return IRK_OK;
+  };
+  CHK(clr(st->V, vb * (st->opt.restart + 1)));
+  CHK(clr(st->Z, vb * st->opt.restart));
+  CHK(clr(st->f, vb));
+  CHK(clr(st->k, vb));
+  CHK(clr(st->tmp, tb));
+  CHK(clr(st->tmp2, tb));
+  const size_t tsz = storage_bytes(st->prec);
+  for (const Level& lev : st->lv) {
+    const size_t pb = lev.g.plane * tsz;
+    CHK(clr(lev.t, pb));
+    CHK(clr(lev.e, pb));
+    CHK(clr(lev.x, pb));
+    CHK(clr(lev.tp, lev.g.plane * (st->prec == 0 ? sizeof(double) : sizeof(float))));
+  }
+  for (const Level& lev : st->ml) {
+    const size_t pb = (size_t)st->s * lev.g.plane * tsz;
+    CHK(clr(lev.t, pb));
+    CHK(clr(lev.e, pb));
+    CHK(clr(lev.x, pb));
+  }
+  return IRK_OK;
+}
+
+int stage_solve_run(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s);
+
 int stage_solve(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s) {
+  const int rc = stage_solve_run(st, f, trans, use_guess, info, s);
+  if (rc == IRK_EBREAKDOWN) {
+    const std::string keep = g_err;
+    (void)clear_work(st, s);
+    g_err = keep;
+  }
+  return rc;
+}
+
+int stage_solve_run(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveInfo& info, hipStream_t s) {
   if (!st->dirk) return fgmres(st, f, trans, use_guess, info, s);
   info = SolveInfo{};
   const int ns = st->s;
@@ -1500,7 +1547,6 @@ void irk_stepper_destroy(irk_stepper* st) {
   dev_free(st->Z);
   dev_free(st->f);
   dev_free(st->k);
-  dev_free(st->kprev);
   dev_free(st->tmp);
   dev_free(st->tmp2);
   dev_free(st->u);
@@ -1667,7 +1713,6 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   alloc_zero(&st->Z, vb * m);
   alloc_zero(&st->f, vb);
   alloc_zero(&st->k, vb);
-  alloc_zero(&st->kprev, vb);
   // scratch planes; at least two, the power iteration keeps x and y in tmp
   const size_t tb = (size_t)std::max(s, 2) * p->g.plane * sizeof(double);
   alloc_zero(&st->tmp, tb);

@@ -254,6 +254,38 @@ def test_enoconv_keeps_last_good_state():
     assert np.array_equal(host(u), u0)
 
 
+@pytest.mark.parametrize("orth,pc", [(P.ORTH_DCGS2, P.PC_GS_LOWER), (P.ORTH_CGS2, P.PC_GS_LOWER),
+                                     (P.ORTH_DCGS2, P.PC_MONOLITHIC)])
+def test_ebreakdown_on_non_finite_data(orth, pc):
+    # a NaN in the stage right-hand side and an infinity in the state are reported as IRK_EBREAKDOWN (the Arnoldi
+    # steps queued ahead of the host's norm check compute on the non-finite values, and the flat vector kernels
+    # then write non-finite values into the boundary ring of the work planes); the stepper clears its work planes
+    # and stays usable: its next solves give the same bits as a new stepper's
+    N, dt = 32, 1e-3
+    kap = synth.grf_kappa(N, 1)
+    tab = P.tableaux.radau_iia(3)
+    _, stp = make(N, kap, tab, dt, rtol=1e-12, orth=orth, precond=pc)
+    f = synth.random_stage_block(N, 3, 4).ravel()
+    bad = f.copy()
+    bad[17] = np.nan
+    with pytest.raises(P.IrkError) as e:
+        stp.solve_stages(dev(bad))
+    assert e.value.code == P.IRK_EBREAKDOWN
+    u0, _ = synth.sine_modes_u0(N, 0)
+    ub = u0.copy()
+    ub[5] = np.inf
+    rc, st = stp.advance(dev(ub), 2, check=False)
+    assert rc == P.IRK_EBREAKDOWN and st["failed_step"] == 0 and st["steps_done"] == 0
+    x, _ = stp.solve_stages(dev(f))
+    _, fresh = make(N, kap, tab, dt, rtol=1e-12, orth=orth, precond=pc)
+    x2, _ = fresh.solve_stages(dev(f))
+    assert np.array_equal(host(x), host(x2))
+    u, u2 = dev(u0), dev(u0)
+    stp.advance(u, 2)
+    fresh.advance(u2, 2)
+    assert np.array_equal(host(u), host(u2))
+
+
 def test_invalid_kappa_rejected():
     N = 16
     kap = np.ones(N * N)
