@@ -308,6 +308,13 @@ int irk_kernel_timer_family(irk_stepper *st, int family, int *launches, double *
 /* The same over all timed families (per-pass model bytes). */
 int irk_kernel_timer_read(irk_stepper *st, int *launches, double *total_ms, double *bytes);
 
+/* Measurement reference (defined by no passage of the paper): y = x for n doubles (device, no
+ * overlap, IRK_EINVAL otherwise; n = 0 does nothing), one 16-byte load and store per thread when
+ * both pointers are 16-byte aligned. The plain streaming kernel against which the solver's kernels
+ * are compared: its bandwidth is the practical ceiling, and its HBM byte counters (2n*8 bytes
+ * known) scale the counters of the others. Only enqueues work. */
+int irk_device_copy(const double *x, double *y, long long n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

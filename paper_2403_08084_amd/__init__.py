@@ -113,7 +113,7 @@ SYMBOLS = [
     "irk_apply_mass", "irk_apply_stiffness", "irk_apply_mass_noalloc", "irk_stepper_create", "irk_stepper_destroy",
     "irk_stepper_refresh", "irk_stage_rhs", "irk_apply_stage_operator", "irk_apply_preconditioner", "irk_vcycle",
     "irk_solve_stages", "irk_advance", "irk_adjoint", "irk_revolve_schedule", "irk_stepper_sizes", "irk_stepper_mu",
-    "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_family", "irk_kernel_timer_read",
+    "irk_stepper_mmg_mu", "irk_kernel_timer", "irk_kernel_timer_family", "irk_kernel_timer_read", "irk_device_copy",
 ]
 
 
@@ -157,6 +157,7 @@ def lib():
     L.irk_kernel_timer.argtypes = [vp, ip, ip]
     L.irk_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ip), dp, dp]
     L.irk_kernel_timer_family.argtypes = [vp, ip, ctypes.POINTER(ip), dp, dp, dp]
+    L.irk_device_copy.argtypes = [vp, vp, ctypes.c_longlong, vp]
     for name in SYMBOLS:
         if name not in ("irk_last_error", "irk_options_default", "irk_problem_destroy", "irk_stepper_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -376,6 +377,15 @@ class Stepper:
                                  _dev_ptr(lam_T, self.n, "lambda_T"), _dev_ptr(lam0), _dev_ptr(grad),
                                  ctypes.byref(st), _stream(stream)))
         return lam0, grad, st.as_dict()
+
+
+def device_copy(x, y, stream=None):
+    """y = x (device float64 vectors of equal length): the library's plain streaming copy, the reference kernel for
+    bandwidth ceilings and counter scaling."""
+    n = int(x.numel())
+    if int(y.numel()) != n:
+        raise ValueError("x and y differ in length")
+    _check(lib().irk_device_copy(_dev_ptr(x, n, "x"), _dev_ptr(y, n, "y"), n, _stream(stream)))
 
 
 def revolve_schedule(nsteps: int, nsnap: int):

@@ -119,6 +119,7 @@ void launch_unpack_elem(const double* src, double* dst, Geom g, hipStream_t st);
 void launch_check_kappa(const double* kappa, int count, int* bad, hipStream_t st);
 void launch_cast_f32(const double* src, float* dst, long count, hipStream_t st);
 void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, hipStream_t st);
+void launch_device_copy(const double* x, double* y, long n, hipStream_t st);
 
 // ---------------------------------------------------------------- stencils (k_stencil.hip)
 // y = (I (x) M + dt*A (x) K) x  (coefficients `a`, row-major s x s); if f != nullptr: y = f - that.

@@ -380,6 +380,22 @@ __global__ void scale_kernel(double* __restrict__ x, long n, const double* __res
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) x[q] *= f;
 }
 
+// Streaming copy, the reference kernel for the bandwidth ceiling and for scaling the HBM byte counters: one 16-byte
+// load and one store per thread over a grid that covers the vector (an odd last value is copied by the first
+// thread); pointers that are not 16-byte aligned take the scalar grid-stride form.
+__global__ __launch_bounds__(256) void device_copy_kernel(const double2* __restrict__ x, double2* __restrict__ y,
+                                                          long n2, const double* __restrict__ xs,
+                                                          double* __restrict__ ys, long n) {
+  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  if (q < n2) y[q] = x[q];
+  if ((n & 1) && q == 0) ys[n - 1] = xs[n - 1];
+}
+
+__global__ __launch_bounds__(256) void device_copy_scalar_kernel(const double* __restrict__ x, double* __restrict__ y,
+                                                                 long n) {
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) y[q] = x[q];
+}
+
 int flat_blocks(long n) {
   long b = (n + 255) / 256;
   if (b > 4096) b = 4096;
@@ -388,6 +404,17 @@ int flat_blocks(long n) {
 }
 
 }  // namespace
+
+void launch_device_copy(const double* x, double* y, long n, hipStream_t st) {
+  if (n <= 0) return;
+  if (((uintptr_t)x | (uintptr_t)y) & 15) {
+    launch_k(device_copy_scalar_kernel, flat_blocks(n), 256, st, x, y, n);
+    return;
+  }
+  const long n2 = n / 2;
+  const long blocks = n2 > 0 ? (n2 + 255) / 256 : 1;
+  launch_k(device_copy_kernel, dim3((unsigned)blocks), 256, st, (const double2*)x, (double2*)y, n2, x, y, n);
+}
 
 void launch_pack(const double* src, double* dst, Geom g, int nplanes, hipStream_t st) {
   launch_k(pack_kernel, dim3(flat_blocks(g.plane), nplanes), 256, st, src, dst, g);

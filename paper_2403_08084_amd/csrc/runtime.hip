@@ -2063,4 +2063,14 @@ int irk_kernel_timer_read(irk_stepper* st, int* launches, double* total_ms, doub
   return irk_kernel_timer_family(st, IRK_KFAM_ALL, launches, total_ms, bytes, nullptr);
 }
 
+int irk_device_copy(const double* x, double* y, long long n, void* stream) {
+  g_err.clear();
+  if (n < 0) return fail(IRK_EINVAL, "n must be >= 0");
+  if (n == 0) return IRK_OK;
+  if (!x || !y) return fail(IRK_EINVAL, "NULL argument");
+  if (x < y + n && y < x + n) return fail(IRK_EINVAL, "x and y overlap");
+  launch_device_copy(x, y, (long)n, S(stream));
+  return check_launch();
+}
+
 }  // extern "C"

@@ -48,3 +48,23 @@ def test_stage_operator(N, name, dt, transpose):
     x = synth.random_stage_block(N, stp.s, 5).ravel()
     y = host(stp.apply_stage_operator(dev(x), transpose=transpose))
     assert rel(y, Acal @ x) < 1e-14
+
+
+@pytest.mark.parametrize("n,xoff,yoff", [(0, 0, 0), (1, 0, 0), (7, 0, 0), (1_000_001, 0, 0), (1_000_000, 1, 0),
+                                         (33, 0, 1), (64, 1, 1)])
+def test_device_copy(n, xoff, yoff):
+    # the measurement reference copy: exact for even and odd lengths, aligned (16-byte path) and offset by one
+    # value (scalar path); nothing outside y is written; overlapping vectors are refused
+    import torch
+
+    src = torch.as_tensor(np.random.default_rng(n).standard_normal(n + 2)).cuda()
+    dst = torch.full((n + 2,), -7.0, dtype=torch.float64, device="cuda")
+    x, y = src[xoff:xoff + n], dst[yoff:yoff + n]
+    P.device_copy(x, y)
+    d = host(dst)
+    assert np.array_equal(d[yoff:yoff + n], host(src)[xoff:xoff + n])
+    assert np.all(d[:yoff] == -7.0) and np.all(d[yoff + n:] == -7.0)
+    if n >= 2:
+        with pytest.raises(P.IrkError) as e:
+            P.device_copy(src[0:n - 1], src[1:n])
+        assert e.value.code == P.IRK_EINVAL
