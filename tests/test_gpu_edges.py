@@ -1,5 +1,5 @@
-"""GPU edge cases: the largest grid in the suite (closed form), the smallest grid, ragged grids whose level sizes
-fit no tile, the largest stage count, empty work."""
+"""GPU edge cases: the largest grids in the suite (closed form), the smallest grid, ragged grids whose level sizes
+fit no tile, the largest stage count, empty work, non-finite data and a device allocation that cannot succeed."""
 import numpy as np
 import pytest
 
@@ -12,10 +12,11 @@ from gpu_util import dev, host, make, rel
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("pc", [P.PC_GS_LOWER, P.PC_MONOLITHIC])
-def test_largest_grid_closed_form(pc):
-    # 2048^2 (4.2M interior nodes, 12.6M stage unknowns), kappa = 1: sine modes decay by R(-dt lam) exactly
-    N, dt, nsteps = 2048, 1e-3, 2
+@pytest.mark.parametrize("N,pc", [(2048, P.PC_GS_LOWER), (2048, P.PC_MONOLITHIC), (4096, P.PC_GS_LOWER)])
+def test_largest_grid_closed_form(N, pc):
+    # 2048^2 (4.2M interior nodes, 12.6M stage unknowns) and 4096^2 (16.8M nodes, 50.3M stage unknowns, ten
+    # multigrid levels), kappa = 1: sine modes decay by R(-dt lam) exactly
+    dt, nsteps = 1e-3, 2
     u0, amps = synth.sine_modes_u0(N, 0)
     _, stp = make(N, np.ones(N * N), P.tableaux.radau_iia(3), dt, rtol=1e-10, precond=pc, mg_precision=P.F32)
     cf = step.closed_form_modes(N, OT.radau_iia(3), dt, nsteps, amps)
