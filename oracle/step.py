@@ -56,13 +56,16 @@ def stages_from_w(A, w):
     return np.linalg.solve(A, np.asarray(w).reshape(s, -1)).ravel()
 
 
-def dirk_solve(M, K, A, dt, rhs, trans=False):
+def dirk_solve(M, K, A, dt, rhs, trans=False, lu=None):
     """Stage-by-stage solve of the coupled system for a lower-triangular A (Section 2.3, DIRK).
 
     (I (x) M + dt A (x) K) k = rhs is block lower triangular, so stage i needs one single-stage
     solve with M + dt a_ii K after moving the already known stages to the right:
         (M + dt a_ii K) k_i = rhs_i - dt K sum_{j<i} a_ij k_j.
     The transposed system (A^T upper triangular) runs backwards: j > i with a_ji.
+    lu: optional dict that keeps one sparse LU factorisation per diagonal entry a_ii across calls
+    (M and K are symmetric, so the transposed system uses the same blocks); without it every stage
+    solve factorises its block afresh.
     """
     A = np.asarray(A, dtype=np.float64)
     s = A.shape[0]
@@ -77,7 +80,12 @@ def dirk_solve(M, K, A, dt, rhs, trans=False):
         for j in known:
             aij = A[j, i] if trans else A[i, j]
             t -= dt * (K @ (aij * k[j]))
-        k[i] = spla.spsolve((M + dt * A[i, i] * K).tocsc(), t)
+        if lu is None:
+            k[i] = spla.spsolve((M + dt * A[i, i] * K).tocsc(), t)
+        else:
+            if A[i, i] not in lu:
+                lu[A[i, i]] = spla.splu((M + dt * A[i, i] * K).tocsc())
+            k[i] = lu[A[i, i]].solve(t)
     return k.ravel()
 
 
@@ -224,7 +232,8 @@ def run(N, kappa, tab, dt, nsteps, u0, F=None, tier="coupled", return_stages=Fal
         Ad = coupled_matrix(M, K, A, dt).toarray()
         solver = lambda r, trans=False: np.linalg.solve(Ad.T if trans else Ad, r)  # noqa: E731
     elif tier == "dirk":
-        solver = lambda r: dirk_solve(M, K, A, dt, r)  # noqa: E731
+        factors = {}
+        solver = lambda r: dirk_solve(M, K, A, dt, r, lu=factors)  # noqa: E731
     else:
         raise ValueError(tier)
     us = [np.asarray(u0, dtype=np.float64).copy()]

@@ -73,6 +73,29 @@ def test_config3_fullsize_gl4(pc):
     _run_fullsize("gl4", P.tableaux.gauss_legendre(4), 5e-4, 20, P.F64, pc, 1e-10)
 
 
+@pytest.mark.parametrize("prec,tol", [(P.F64, 1e-10), (P.F32, 1e-8)])
+def test_dirk_fullsize(prec, tol):
+    # the stage-by-stage path (one single-stage FGMRES per stage, known stages moved to the right) on the 1024^2
+    # variable-kappa workload with the Alexander SDIRK(3), against the oracle's stage-by-stage direct tier
+    N, dt, nsteps = 1024, 1e-3, 5
+    key = ("dirk", N, dt, nsteps)
+    if key not in _ORACLE:
+        t0 = time.time()
+        _ORACLE[key] = step.run(N, synth.grf_kappa(N, 1), OT.alexander(), dt, nsteps, synth.sine_modes_u0(N, 0)[0],
+                                tier="dirk")
+        print(f"oracle dirk {N}^2 {nsteps} steps: {time.time() - t0:.1f} s", flush=True)
+    ref = _ORACLE[key]
+    _, stp = make(N, synth.grf_kappa(N, 1), P.tableaux.alexander(), dt, mg_precision=prec, rtol=1e-11,
+                  stage_type=P.STAGE_DIRK)
+    u = dev(ref[0])
+    errs = []
+    for k in range(1, nsteps + 1):
+        stp.advance(u, 1)
+        errs.append(rel(host(u), ref[k]))
+    print(f"dirk prec {prec}: max over steps {max(errs):.2e}")
+    assert max(errs) < tol, errs
+
+
 def test_config2_fullsize_closed_form():
     N, dt, nsteps = 512, 1e-3, 50
     u0, amps = synth.sine_modes_u0(N, 0)

@@ -135,6 +135,21 @@ def test_dirk_sequential_solve():
     f = np.random.default_rng(8).standard_normal(3 * (N - 1) ** 2)
     kt = step.CoupledLU(M, K, A, dt).solve(f, trans=True)
     assert np.linalg.norm(step.dirk_solve(M, K, A, dt, f, trans=True) - kt) < 1e-12 * np.linalg.norm(kt)
+    # with one factorisation kept per diagonal entry (the form the run tier uses), forward and transposed, on a
+    # tableau whose diagonal entries differ too; the second round reuses the kept factors
+    for tab2 in (tab, T.wsodirk433()):
+        A2 = tab2["A"]
+        s2 = A2.shape[0]
+        f2 = np.random.default_rng(9).standard_normal(s2 * (N - 1) ** 2)
+        k2 = step.CoupledLU(M, K, A2, dt).solve(step.stage_rhs(K, u, s2))
+        kt2 = step.CoupledLU(M, K, A2, dt).solve(f2, trans=True)
+        lu = {}
+        for _ in range(2):
+            r = step.dirk_solve(M, K, A2, dt, step.stage_rhs(K, u, s2), lu=lu)
+            assert np.linalg.norm(r - k2) < 1e-12 * np.linalg.norm(k2)
+            rt = step.dirk_solve(M, K, A2, dt, f2, trans=True, lu=lu)
+            assert np.linalg.norm(rt - kt2) < 1e-12 * np.linalg.norm(kt2)
+        assert len(lu) == len(set(np.diag(A2)))
     with pytest.raises(ValueError):
         step.dirk_solve(M, K, T.radau_iia(2)["A"], dt, f[: 2 * (N - 1) ** 2])
 
