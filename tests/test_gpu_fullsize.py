@@ -49,10 +49,10 @@ def _oracle_states(tname, dt, nsteps, N=1024):
     return _ORACLE[key]
 
 
-def _run_fullsize(tname, tab, dt, nsteps, prec, pc, tol, N=1024):
+def _run_fullsize(tname, tab, dt, nsteps, prec, pc, tol, N=1024, **opts):
     ref = _oracle_states(tname, dt, nsteps, N)
     kap = synth.grf_kappa(N, 1)
-    _, stp = make(N, kap, tab, dt, mg_precision=prec, precond=pc, rtol=1e-10)
+    _, stp = make(N, kap, tab, dt, mg_precision=prec, precond=pc, rtol=1e-10, **opts)
     u = dev(ref[0])
     errs = []
     for k in range(1, nsteps + 1):
@@ -66,6 +66,14 @@ def _run_fullsize(tname, tab, dt, nsteps, prec, pc, tol, N=1024):
 @pytest.mark.parametrize("prec,tol", [(P.F64, 1e-10), (P.F32, 1e-8), (P.BF16, 1e-8)])
 def test_config4_fullsize(prec, tol):
     _run_fullsize("radau3", P.tableaux.radau_iia(3), 1e-3, 20, prec, P.PC_GS_LOWER, tol)
+
+
+@pytest.mark.parametrize("pc,split", [(P.PC_RANA_LD, P.SPLIT_IA), (P.PC_MONOLITHIC, P.SPLIT_AI),
+                                      (P.PC_MONOLITHIC, P.SPLIT_IA)])
+def test_config4_fullsize_variants(pc, split):
+    # the bench's variants of the mixed-precision workload: Rana-LD in the IA form and the monolithic cycle; the
+    # IA form's unknowns are w = (A (x) I) k, but u^{n+1} is the same, so the same oracle states apply
+    _run_fullsize("radau3", P.tableaux.radau_iia(3), 1e-3, 20, P.F32, pc, 1e-8, splitting=split)
 
 
 @pytest.mark.parametrize("pc", [P.PC_JACOBI, P.PC_GS_LOWER])
