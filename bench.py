@@ -28,7 +28,8 @@ Extra JSON objects:
                      FP64 (against the closed form) and 1024^2 Gauss-Legendre(4) with block
                      Jacobi vs block Gauss-Seidel (against the oracle);
   "adjoint"          the gradient workload (512^2, 40 steps, 8 snapshots, FP64,
-                     J = 1/2 |u_N - u_*|_M^2): forward and gradient wall times;
+                     J = 1/2 |u_N - u_*|_M^2): forward and gradient wall times, the whole
+                     gradient and lambda_0 against the oracle's (CPU leg);
   "cpu_baseline"     the CPU oracle on the same workload, host described.
 
 Other workloads of the same method: --tableau, --dt, --kappa, --N, --steps,
@@ -270,7 +271,7 @@ def adjoint_timing(P, torch, synth, N=512, steps=40, nsnap=8, dt=1e-3):
     J = 0.5 * float(torch.dot(d, lam))
     torch.cuda.synchronize()
     ev[2].record()
-    _, grad, ast = stp.adjoint(u0, steps, nsnap, lam)
+    lam0, grad, ast = stp.adjoint(u0, steps, nsnap, lam)
     ev[3].record()
     torch.cuda.synchronize()
     fwd, gms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
@@ -280,12 +281,13 @@ def adjoint_timing(P, torch, synth, N=512, steps=40, nsnap=8, dt=1e-3):
            "J": J, "forward_ms": fwd, "gradient_ms": gms, "gradient_over_forward": gms / fwd,
            "forward_its": fst["fgmres_its_total"], "adjoint_its": ast["fgmres_its_total"],
            "forward_advances": ast["forward_advances"]}
-    return out, grad.cpu().numpy()
+    return out, grad.cpu().numpy(), lam0.cpu().numpy()
 
 
 def adjoint_error(grad, J):
     """Gradient against the oracle's stored store-all gradient (tests/golden, written by a script that calls
-    only the oracle): an estimate from its seeded samples, sketch and norm."""
+    only the oracle): an estimate from its seeded samples, sketch and norm (the whole-vector comparison runs in
+    the CPU leg, cpu_leg_adjoint)."""
     import numpy as np
 
     import synth
@@ -318,6 +320,29 @@ def host_cpu():
     except AttributeError:
         usable = os.cpu_count()
     return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
+def cpu_leg_adjoint(grad, lam0, J, N=512, steps=40, dt=1e-3):
+    """The gradient workload's whole gradient and lambda_0 against the oracle's (eigen-decoupled direct tier,
+    forward, target and transposed solves; about half a minute on the host)."""
+    import numpy as np
+
+    from oracle import adjoint, step
+    from oracle import tableaux as T
+    import synth
+
+    tab = T.radau_iia(3)
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    t0 = time.time()
+    ustar = step.run(N, synth.grf_kappa(N, 2), tab, dt, steps, u0, tier="decoupled")[-1]
+    fwd = adjoint.forward(N, kap, tab, dt, steps, u0, tier="decoupled")
+    Jo, lamN = adjoint.objective(fwd[2], fwd[0][-1], ustar)
+    lam0o, grado = adjoint.gradient(N, kap, tab, dt, steps, u0, lamN, tier="decoupled", fwd=fwd)
+    return {"kind": "whole vectors against the oracle's gradient (eigen-decoupled direct tier) computed in this run",
+            "grad_rel_l2": float(np.linalg.norm(grad - grado) / np.linalg.norm(grado)),
+            "lam0_rel_l2": float(np.linalg.norm(lam0 - lam0o) / np.linalg.norm(lam0o)),
+            "J_rel": abs(J - Jo) / abs(Jo), "oracle_s": time.time() - t0}
 
 
 def cpu_leg(args, want_config2, want_config3):
@@ -487,8 +512,8 @@ def main(argv=None):
             r3["stepper"].close()
         out["configs"] = cfg
     if not args.no_adjoint and not args.no_variants:
-        adj, grad = adjoint_timing(P, torch, synth)
-        adj["error_vs_oracle"] = adjoint_error(grad, adj["J"])
+        adj, adj_grad, adj_lam0 = adjoint_timing(P, torch, synth)
+        adj["error_vs_oracle"] = adjoint_error(adj_grad, adj["J"])
         out["adjoint"] = adj
     if not args.no_cpu_baseline and N <= ORACLE_MAX_N and distinct_eigenvalues(tab["A"]):
         leg = cpu_leg(args, want_config2=want_cfg, want_config3=want_cfg)
@@ -506,6 +531,10 @@ def main(argv=None):
             out["configs"]["oracle"] = ("512^2: closed form of the discrete sine modes; GL(4): eigen-decoupled "
                                         f"direct solve ({leg.get('config3_oracle_s', 0):.0f} s on the host)")
         out["oracle"] = "eigen-decoupled sparse direct solve of the stage-coupled system (FP64, CPU)"
+        if "adjoint" in out:
+            est = out["adjoint"]["error_vs_oracle"]
+            out["adjoint"]["error_vs_oracle"] = cpu_leg_adjoint(adj_grad, adj_lam0, out["adjoint"]["J"])
+            out["adjoint"]["error_vs_stored_summary"] = est
     print(json.dumps(out))
 
 
