@@ -2068,7 +2068,8 @@ int irk_device_copy(const double* x, double* y, long long n, void* stream) {
   if (n < 0) return fail(IRK_EINVAL, "n must be >= 0");
   if (n == 0) return IRK_OK;
   if (!x || !y) return fail(IRK_EINVAL, "NULL argument");
-  if (x < y + n && y < x + n) return fail(IRK_EINVAL, "x and y overlap");
+  const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, nb = (uintptr_t)n * sizeof(double);
+  if (xa < ya + nb && ya < xa + nb) return fail(IRK_EINVAL, "x and y overlap");
   launch_device_copy(x, y, (long)n, S(stream));
   return check_launch();
 }
