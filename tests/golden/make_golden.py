@@ -1,17 +1,17 @@
 #!/usr/bin/env python3
-"""Write the full-size reference sketches used by the GPU parity tests and the benchmark.
+"""Write the stored summary of the oracle's gradient for the 512^2 gradient workload (config 5), used by the GPU
+parity test and the benchmark beside their whole-vector comparisons with the oracle computed in the run.
 
-Calls only the CPU oracle (oracle/) and the seeded input generators (synth/).
-The full 1024^2 stage-coupled LU does not fit in memory, so the oracle's
-eigen-decoupled direct tier (exact up to rounding, pinned against the coupled LU
-at smaller sizes) produces the reference. Each stored vector u is summarised as
+Calls only the CPU oracle (oracle/) and the seeded input generators (synth/). The gradient comes from the
+oracle's coupled sparse LU (forward and transposed solves, all states stored), an independent tier from the
+eigen-decoupled one the tests run live. Each stored vector u is summarised as
   * its 2-norm and max-norm,
   * the values at 1024 seeded indices,
   * 8 projections <g_k, u> onto seeded Gaussian vectors g_k (a sketch: for any
     error e, the projections are N(0, |e|^2) draws, so they bound |e|/|u|).
 The sketch vectors are regenerated from their seed by the readers (sketch_vectors).
 
-Usage: python tests/golden/make_golden.py [config4|config3|all]
+Usage: python tests/golden/make_golden.py
 """
 from __future__ import annotations
 
@@ -47,36 +47,6 @@ def sketch_vectors(n: int) -> np.ndarray:
 def summarise(u: np.ndarray, G: np.ndarray, idx: np.ndarray) -> dict:
     return {"norm2": float(np.linalg.norm(u)), "norminf": float(np.abs(u).max()),
             "samples": [float(v) for v in u[idx]], "sketch": [float(v) for v in G @ u]}
-
-
-def run(name: str, tab_name: str, dt: float, nsteps: int, N: int = 1024, keep=(1, 20)):
-    from oracle import step
-    from oracle import tableaux as T
-    import synth
-
-    tab = {"radau3": T.radau_iia(3), "gl4": T.gauss_legendre(4)}[tab_name]
-    kap = synth.grf_kappa(N, 1)
-    u0, _ = synth.sine_modes_u0(N, 0)
-    t0 = time.time()
-    us = step.run(N, kap, tab, dt, nsteps, u0, tier="decoupled")
-    elapsed = time.time() - t0
-    n = (N - 1) ** 2
-    idx = sample_indices(n)
-    G = sketch_vectors(n)
-    out = {
-        "workload": f"{name}: Q1 {N}x{N}, kappa = exp(GRF seed 1, std 1, corr 0.1), u0 = 16 sine modes (seed 0), "
-                    f"{tab['name']}, dt={dt}, {nsteps} steps",
-        "oracle": "eigen-decoupled sparse direct (oracle.step.DecoupledLU), FP64",
-        "N": N, "n": n, "dt": dt, "nsteps": nsteps, "tableau": tab_name,
-        "sample_seed": SAMPLE_SEED, "sketch_seed": SKETCH_SEED, "n_samples": int(idx.size), "n_sketch": N_SKETCH,
-        "indices": [int(i) for i in idx],
-        "steps": {str(k): summarise(us[k], G, idx) for k in keep if k <= nsteps},
-        "oracle_seconds": elapsed,
-    }
-    path = os.path.join(HERE, f"{name}.json")
-    with open(path, "w") as f:
-        json.dump(out, f)
-    print(f"wrote {path} ({elapsed:.1f} s)")
 
 
 def run_adjoint(name: str = "config5_adjoint_512", N: int = 512, dt: float = 1e-3, nsteps: int = 40):
@@ -120,13 +90,7 @@ def run_adjoint(name: str = "config5_adjoint_512", N: int = 512, dt: float = 1e-
 
 
 def main():
-    which = sys.argv[1] if len(sys.argv) > 1 else "all"
-    if which in ("config5", "all"):
-        run_adjoint()
-    if which in ("config4", "all"):
-        run("config4_radau3_1024", "radau3", 1e-3, 20)
-    if which in ("config3", "all"):
-        run("config3_gl4_1024", "gl4", 5e-4, 20)
+    run_adjoint()
 
 
 if __name__ == "__main__":
