@@ -1,5 +1,5 @@
 """Host-side contract of bench.py: the one-GPU exit, the counter summary it reads only while the kernels are
-unchanged, the full-vector error metric, and its CPU oracle leg on a small grid."""
+unchanged, the full-vector error metric, and its CPU oracle legs (workload and gradient) on small grids."""
 import json
 import os
 import subprocess
@@ -61,3 +61,25 @@ def test_cpu_leg_on_a_small_grid():
     assert len(refs) == 3 and refs[0].shape == (15 * 15,)
     # the solution decays (heat equation, zero Dirichlet data)
     assert np.linalg.norm(refs[-1]) < np.linalg.norm(refs[0])
+
+
+def test_cpu_leg_adjoint_compares_whole_vectors():
+    # the oracle's coupled-LU gradient on a small grid, handed in as if it came from the GPU: the CPU leg's
+    # decoupled-tier gradient agrees to rounding; a perturbation of one element shows up as its relative size
+    from oracle import adjoint, step
+    from oracle import tableaux as T
+    import synth
+
+    N, steps, dt = 16, 3, 1e-3
+    tab = T.radau_iia(3)
+    kap = synth.grf_kappa(N, 1)
+    u0, _ = synth.sine_modes_u0(N, 0)
+    ustar = step.run(N, synth.grf_kappa(N, 2), tab, dt, steps, u0)[-1]
+    fwd = adjoint.forward(N, kap, tab, dt, steps, u0)
+    J, lamN = adjoint.objective(fwd[2], fwd[0][-1], ustar)
+    lam0, g = adjoint.gradient(N, kap, tab, dt, steps, u0, lamN, fwd=fwd)
+    e = bench.cpu_leg_adjoint(g, lam0, J, N=N, steps=steps, dt=dt)
+    assert e["grad_rel_l2"] < 1e-10 and e["lam0_rel_l2"] < 1e-10 and e["J_rel"] < 1e-10
+    g2 = g.copy()
+    g2[7] += 1e-3 * np.linalg.norm(g)
+    assert abs(bench.cpu_leg_adjoint(g2, lam0, J, N=N, steps=steps, dt=dt)["grad_rel_l2"] - 1e-3) < 1e-6
