@@ -61,6 +61,13 @@ def test_argument_validation_before_device_work():
     assert L.irk_advance(None, None, None, 1, None, None) == P.IRK_EINVAL
     assert L.irk_stepper_sizes(None, None, None, None) == P.IRK_EINVAL
     assert L.irk_kernel_timer(None, 0, 1) == P.IRK_EINVAL
+    # the copy reference: a negative length, NULL vectors and overlapping vectors are refused before any launch;
+    # an empty copy does nothing
+    assert L.irk_device_copy(ctypes.c_void_p(64), ctypes.c_void_p(4096), -1, None) == P.IRK_EINVAL
+    assert L.irk_device_copy(None, ctypes.c_void_p(4096), 4, None) == P.IRK_EINVAL
+    assert L.irk_device_copy(ctypes.c_void_p(64), ctypes.c_void_p(64 + 8 * 3), 4, None) == P.IRK_EINVAL
+    assert b"overlap" in L.irk_last_error()
+    assert L.irk_device_copy(None, None, 0, None) == P.IRK_OK
 
 
 def test_product_tableaux_match_oracle_collocation():
