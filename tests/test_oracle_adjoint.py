@@ -69,3 +69,19 @@ def test_gradient_taylor_remainder():
         rem.append(abs(_J(N, logk + h * d, tab, dt, nsteps, u0, ustar) - J0 - h * (g @ d)))
     r1, r2 = rem[0] / rem[1], rem[1] / rem[2]
     assert 3.3 < r1 < 4.8 and 3.3 < r2 < 4.8
+
+
+def test_decoupled_tier_gradient_equals_coupled():
+    # the eigen-decoupled tier (used for the 512^2 gradient workload) gives the coupled LU's states, lam_0 and
+    # gradient to rounding: its transposed solves are pinned here through the whole reverse sweep
+    N, nsteps, dt = 10, 4, 2e-3
+    tab, logk, u0, ustar = _setup(N, nsteps, dt)
+    kap = np.exp(logk)
+    res = {}
+    for tier in ("coupled", "decoupled"):
+        fwd = adjoint.forward(N, kap, tab, dt, nsteps, u0, tier=tier)
+        J, lamN = adjoint.objective(fwd[2], fwd[0][-1], ustar)
+        lam0, g = adjoint.gradient(N, kap, tab, dt, nsteps, u0, lamN, tier=tier, fwd=fwd)
+        res[tier] = (fwd[0][-1], J, lam0, g)
+    for a, b in zip(res["coupled"], res["decoupled"]):
+        assert np.linalg.norm(np.atleast_1d(a) - np.atleast_1d(b)) < 1e-12 * np.linalg.norm(np.atleast_1d(a))
