@@ -11,10 +11,15 @@ from gpu_util import dev, host, make
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec,pc,split", [(P.F32, P.PC_GS_LOWER, P.SPLIT_AI), (P.F64, P.PC_RANA_LD, P.SPLIT_AI),
-                                           (P.BF16, P.PC_GS_LOWER, P.SPLIT_IA), (P.F32, P.PC_MONOLITHIC, P.SPLIT_AI)])
-def test_refresh_equals_a_new_stepper(prec, pc, split):
-    N, dt, nsteps = 64, 1e-3, 3
+# 512^2 has five levels: the three-level DOWN/UP kernels, whose level diffusivities the refresh rebuilds, run too,
+# and the monolithic cycle's finest level takes its large-tile kernels
+@pytest.mark.parametrize("N,prec,pc,split", [(64, P.F32, P.PC_GS_LOWER, P.SPLIT_AI), (64, P.F64, P.PC_RANA_LD, P.SPLIT_AI),
+                                             (64, P.BF16, P.PC_GS_LOWER, P.SPLIT_IA),
+                                             (64, P.F32, P.PC_MONOLITHIC, P.SPLIT_AI),
+                                             (512, P.F32, P.PC_GS_LOWER, P.SPLIT_AI),
+                                             (512, P.F32, P.PC_MONOLITHIC, P.SPLIT_AI)])
+def test_refresh_equals_a_new_stepper(N, prec, pc, split):
+    dt, nsteps = 1e-3, 3
     k1, k2 = synth.grf_kappa(N, 1), synth.grf_kappa(N, 2)
     u0, _ = synth.sine_modes_u0(N, 0)
     opts = dict(mg_precision=prec, precond=pc, splitting=split, rtol=1e-10)
