@@ -126,6 +126,9 @@ void launch_device_copy(const double* x, double* y, long n, hipStream_t st);
 // ia: y = (A (x) M + dt*I (x) K) x instead (the IA form passes A^{-1} as `a`).
 void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
                            const Coefs& a, double dt, hipStream_t st, bool ia = false);
+// the same with FP32 x (the mixed form's flexible basis), read into FP64 arithmetic
+void launch_stage_operator(const float* x, double* y, const double* f, const double* kappa, Geom g, int s,
+                           const Coefs& a, double dt, hipStream_t st, bool ia = false);
 // f_i = -K u + F (F may be null), i = 0..s-1
 // f (and f2 if not NULL: a second copy) = -K u + F in every stage plane
 void launch_stage_rhs(const double* u, const double* F, double* f, const double* kappa, Geom g, int s, hipStream_t st,
@@ -136,6 +139,9 @@ void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipSt
 // t = vmul * vscale * v - dt * Op * sum_{q<nz} row[q] z_q  (z_q planes at z + q*plane; vscale: device scalar or
 // null = 1; Op = K, or M if mass)
 void launch_gs_couple(const double* v, const double* vscale, const double* z, int nz, const Coefs& row, double dt,
+                      const double* kappa, double* t, Geom g, hipStream_t st, int mass = 0, double vmul = 1.0);
+// the same with FP32 z planes
+void launch_gs_couple(const double* v, const double* vscale, const float* z, int nz, const Coefs& row, double dt,
                       const double* kappa, double* t, Geom g, hipStream_t st, int mass = 0, double vmul = 1.0);
 // u += dt * sum_i b_i k_i
 void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st);
@@ -157,7 +163,8 @@ void launch_scale(double* x, long n, const double* inv_norm2_src, hipStream_t st
 // Block Gauss-Seidel coupling folded into the finest-level kernels: their right-hand side becomes
 // t = tscale * v - dt * K * sum_{q<nz} a[q] z_q  (z_q = z + q*zstride, FP64 padded planes).
 struct Couple {
-  const double* z = nullptr;  // first coupled stage plane
+  const void* z = nullptr;    // first coupled stage plane
+  int z_f32 = 0;              // the coupled planes are FP32 (the mixed form's flexible basis), else FP64
   long zstride = 0;
   int nz = 0;                 // number of coupled stages; 0: no coupling
   int mass = 0;               // coupling operator: 0 = stiffness K (element kappa), 1 = mass M
@@ -173,12 +180,13 @@ struct Couple {
 void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale, void* x, void* tc, void* tout,
                     const void* kappa, Geom g, Geom gc, const MGCoef& c, const Couple& cp, hipStream_t st);
 // UP: x0 = x + P e, post-smooth, write out. finest: t is the compute-type right-hand side stored by DOWN and out
-// is the FP64 result; otherwise t and out are level storage.
+// is the FP64 result (FP32 with out_f32: the mixed form's flexible basis, which holds the same values, since the
+// smoother computes in FP32); otherwise t and out are level storage.
 void launch_mg_up(int prec, bool finest, const void* t, const void* x, const void* e, void* out, const void* kappa,
-                  Geom g, Geom gc, const MGCoef& c, hipStream_t st);
-// coarsest level: out = Binv * t on the interior nodes
+                  Geom g, Geom gc, const MGCoef& c, hipStream_t st, bool out_f32 = false);
+// coarsest level: out = Binv * t on the interior nodes (io_is_f64: FP64 t and out; out FP32 with out_f32)
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
-                      hipStream_t st);
+                      hipStream_t st, bool out_f32 = false);
 
 // The three levels A, B = A/2, C = B/2 above the coarsest level D in one launch each way. Index 0..3 = A..D.
 // DOWN3 reads t[0] and writes x[0..2], t[1..3]; UP3 reads e[3], t[0..2], x[0..2] and writes e[0].
@@ -198,12 +206,13 @@ void launch_mg_up3(int prec, const ThreeLevels& z, hipStream_t st);
 // DOWN: Chebyshev pre-smoothing from zero of Acal x = ts t, writes x and the restricted residual tc.
 void launch_mmg_down(int prec, bool t_f64, const void* t, const double* tscale, void* x, void* tc, const void* kap,
                      Geom g, Geom gc, const MMGCoef& c, hipStream_t st);
-// UP: x0 = x + (I (x) P) e, Chebyshev post-smoothing, writes out.
+// UP: x0 = x + (I (x) P) e, Chebyshev post-smoothing, writes out (with io_f64 and out_f32: FP32 out).
 void launch_mmg_up(int prec, bool io_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
-                   const void* kap, Geom g, Geom gc, const MMGCoef& c, hipStream_t st);
-// coarsest level: out = Cinv (ts t) over the s (N-1)^2 stage-major unknowns (<= kMaxCoarse)
+                   const void* kap, Geom g, Geom gc, const MMGCoef& c, hipStream_t st, bool out_f32 = false);
+// coarsest level: out = Cinv (ts t) over the s (N-1)^2 stage-major unknowns (<= kMaxCoarse); out_f32 (with t_f64):
+// FP32 out whatever the storage type
 void launch_mmg_coarse(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, void* out,
-                       const void* Cinv, Geom g, int s, hipStream_t st);
+                       const void* Cinv, Geom g, int s, hipStream_t st, bool out_f32 = false);
 // FP64 set-up: mode 0 out = C^{-1} Acal x, 1 out = Acal x, 2 out = C x
 void launch_mmg_apply(const double* x, double* out, const double* kap, Geom g, const MMGCoef& c, int mode,
                       hipStream_t st);
@@ -211,6 +220,7 @@ void launch_mmg_apply(const double* x, double* out, const double* kap, Geom g, c
 // ---------------------------------------------------------------- Krylov (k_krylov.hip)
 struct OrthoArgs {
   const double* V;       // basis vectors V_k = V + k*vstride
+  const float* Vf;       // if set (update passes only, coef set, no dots): the basis is FP32 at Vf + k*vstride
   long vstride;
   int nv;                // number of basis vectors (0..kMaxRestart)
   double* w;             // vector updated in place when coef != nullptr

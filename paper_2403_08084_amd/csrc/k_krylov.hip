@@ -53,7 +53,7 @@ __device__ __forceinline__ void block_reduce(const double (&vals)[CNT], double* 
   __syncthreads();
 }
 
-template <int NV, int MODE, int U>
+template <int NV, int MODE, int U, bool VF>
 __device__ __forceinline__ void process(const OrthoArgs& a, const double (&c)[NV > 0 ? NV : 1], long q0, long stride,
                                         double (&acc)[NV + 1]) {
   constexpr bool AX = (MODE == AXPY_DOTS || MODE == AXPY);
@@ -68,7 +68,8 @@ __device__ __forceinline__ void process(const OrthoArgs& a, const double (&c)[NV
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int k = 0; k < NV; ++k) v[u][k] = a.V[k * a.vstride + q0 + u * stride];
+      for (int k = 0; k < NV; ++k)
+        v[u][k] = VF ? (double)a.Vf[k * a.vstride + q0 + u * stride] : a.V[k * a.vstride + q0 + u * stride];
   }
   if (AX) {
 #pragma unroll
@@ -88,7 +89,7 @@ __device__ __forceinline__ void process(const OrthoArgs& a, const double (&c)[NV
   for (int u = 0; u < U; ++u) acc[NV] += wv[u] * wv[u];
 }
 
-template <int NV, int MODE>
+template <int NV, int MODE, bool VF>
 __global__ __launch_bounds__(NT) void ortho_kernel(OrthoArgs a, ReduceWork rw) {
   if (a.skip && *a.skip == 0) return;
   constexpr bool AX = (MODE == AXPY_DOTS || MODE == AXPY);
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(NT) void ortho_kernel(OrthoArgs a, ReduceWork rw) {
   const long stride = (long)gridDim.x * NT;
   const long len = a.len;
   long q0 = (long)blockIdx.x * NT + threadIdx.x;
-  for (; q0 + (U - 1) * stride < len; q0 += U * stride) process<NV, MODE, U>(a, c, q0, stride, acc);
-  for (; q0 < len; q0 += stride) process<NV, MODE, 1>(a, c, q0, stride, acc);
+  for (; q0 + (U - 1) * stride < len; q0 += U * stride) process<NV, MODE, U, VF>(a, c, q0, stride, acc);
+  for (; q0 < len; q0 += stride) process<NV, MODE, 1, VF>(a, c, q0, stride, acc);
 
   __shared__ double red[(NV + 1) * NW];
   __shared__ double tot[NV + 1];
@@ -344,19 +345,20 @@ using KernelFn = void (*)(OrthoArgs, ReduceWork);
 using FinishFn = void (*)(OrthoArgs, ReduceWork, int);
 
 template <int NV>
-KernelFn pick(int mode) {
+KernelFn pick(int mode, bool vf) {
+  if (vf) return ortho_kernel<NV, AXPY, true>;  // FP32 basis: update passes only
   switch (mode) {
-    case DOTS: return ortho_kernel<NV, DOTS>;
-    case AXPY_DOTS: return ortho_kernel<NV, AXPY_DOTS>;
-    default: return ortho_kernel<NV, AXPY>;
+    case DOTS: return ortho_kernel<NV, DOTS, false>;
+    case AXPY_DOTS: return ortho_kernel<NV, AXPY_DOTS, false>;
+    default: return ortho_kernel<NV, AXPY, false>;
   }
 }
 
 template <int... I>
 struct Table {
-  static KernelFn get(int nv, int mode) {
+  static KernelFn get(int nv, int mode, bool vf) {
     KernelFn out = nullptr;
-    ((nv == I + 1 ? (out = pick<I + 1>(mode), 0) : 0), ...);
+    ((nv == I + 1 ? (out = pick<I + 1>(mode, vf), 0) : 0), ...);
     return out;
   }
   static FinishFn fin(int nv) {
@@ -383,18 +385,20 @@ void launch_ortho(const OrthoArgs& a, const ReduceWork& rw, hipStream_t st, hipE
     b.nv = 0;
     // with events, they are attached to the dispatch itself (kernel start/end timestamps)
     if (ev0)
-      hipExtLaunchKernelGGL(ortho_kernel<0, NORM>, dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, b, rw);
+      hipExtLaunchKernelGGL(ortho_kernel<0, NORM, false>, dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, b, rw);
     else
-      ortho_kernel<0, NORM><<<nb, NT, 0, st>>>(b, rw);
+      ortho_kernel<0, NORM, false><<<nb, NT, 0, st>>>(b, rw);
     launch_k(finish_kernel<0>, dim3(1), dim3(NF), st, b, rw, nb);
     return;
   }
   const int mode = (ax && dt) ? AXPY_DOTS : (ax ? AXPY : DOTS);
+  // an FP32 basis is read by update passes alone (the solution update x = Z y)
+  const bool vf = a.Vf != nullptr && mode == AXPY;
   using T = decltype(make_table(std::make_integer_sequence<int, 32>{}));
   if (ev0)
-    hipExtLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a, rw);
+    hipExtLaunchKernelGGL(T::get(a.nv, mode, vf), dim3(nb), dim3(NT), 0, st, ev0, ev1, 0, a, rw);
   else
-    hipLaunchKernelGGL(T::get(a.nv, mode), dim3(nb), dim3(NT), 0, st, a, rw);
+    hipLaunchKernelGGL(T::get(a.nv, mode, vf), dim3(nb), dim3(NT), 0, st, a, rw);
   launch_k(T::fin(a.nv), dim3(1), dim3(NF), st, a, rw, nb);
 }
 

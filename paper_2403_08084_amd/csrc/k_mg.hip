@@ -197,7 +197,7 @@ __device__ __forceinline__ void couple_rows(const TC* W, int l, int r0, const TC
 // the coarse nodes of a tile (fine positions 2I, 2J) are whole.
 // tout (optional): the level's right-hand side as the smoother sees it (scaled, coupling applied), stored on the
 // tile in the compute type for the UP kernel of the same V-cycle.
-template <typename TV, typename TS, typename TC, int DEG, int NW, int RW, bool COUPLE>
+template <typename TV, typename TS, typename TC, int DEG, int NW, int RW, bool COUPLE, typename TZ>
 __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ t, const double* __restrict__ tscale,
                                                          TS* __restrict__ xout, TS* __restrict__ tc,
                                                          TC* __restrict__ tout, const TC* __restrict__ kap, Geom g,
@@ -241,10 +241,10 @@ __global__ __launch_bounds__(NW* WL) void mg_down_kernel(const TV* __restrict__ 
 #pragma unroll
     for (int q = 0; q < kMaxStages - 1; ++q) {
       if (q < cp.nz) {
-        const double* zq = cp.z + q * cp.zstride;
+        const TZ* zq = (const TZ*)cp.z + q * cp.zstride;
         double zv[RW];
 #pragma unroll
-        for (int r = 0; r < RW; ++r) zv[r] = zq[p[r]];
+        for (int r = 0; r < RW; ++r) zv[r] = (double)zq[p[r]];
 #pragma unroll
         for (int r = 0; r < RW; ++r) acc[r] += cp.a[q] * zv[r];
       }
@@ -930,41 +930,46 @@ dim3 level_grid(const Geom& g) {
   return dim3(((g.N - 1 + TX - 1) / TX) * ((g.N - 1 + TY - 1) / TY));
 }
 
-template <typename TV, typename TS, typename TC, bool CP, int NW, int RW>
+template <typename TV, typename TS, typename TC, bool CP, typename TZ, int NW, int RW>
 void down_shape(const TV* tt, const double* tscale, TS* xx, TS* cc, TC* to, const TC* kk, Geom g, Geom gc,
                 const MGCoef& c, const Couple& cp, hipStream_t st) {
   constexpr int B = NW * WL, C = CP ? 1 : 0;
   switch (c.deg) {
     case 1:
-      launch_k(mg_down_kernel<TV, TS, TC, 1, NW, RW, CP>, level_grid<NW, RW, 2 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      launch_k(mg_down_kernel<TV, TS, TC, 1, NW, RW, CP, TZ>, level_grid<NW, RW, 2 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
       break;
     case 2:
-      launch_k(mg_down_kernel<TV, TS, TC, 2, NW, RW, CP>, level_grid<NW, RW, 3 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      launch_k(mg_down_kernel<TV, TS, TC, 2, NW, RW, CP, TZ>, level_grid<NW, RW, 3 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
       break;
     default:
-      launch_k(mg_down_kernel<TV, TS, TC, 3, NW, RW, CP>, level_grid<NW, RW, 4 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
+      launch_k(mg_down_kernel<TV, TS, TC, 3, NW, RW, CP, TZ>, level_grid<NW, RW, 4 + C>(g), B, st, tt, tscale, xx, cc, to, kk, g, gc, c, cp);
       break;
   }
 }
 
-template <typename TV, typename TS, typename TC, bool CP>
+template <typename TV, typename TS, typename TC, bool CP, typename TZ>
 void down_launch(const TV* tt, const double* tscale, TS* xx, TS* cc, TC* to, const TC* kk, Geom g, Geom gc,
                  const MGCoef& c, const Couple& cp, hipStream_t st) {
   if (g.N >= kBigLevel)
-    down_shape<TV, TS, TC, CP, DNWB, DRWB>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
+    down_shape<TV, TS, TC, CP, TZ, DNWB, DRWB>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
   else if (g.N >= kMidLevel)
-    down_shape<TV, TS, TC, CP, DNWM, DRWM>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
+    down_shape<TV, TS, TC, CP, TZ, DNWM, DRWM>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
   else
-    down_shape<TV, TS, TC, CP, DNWS, DRWS>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
+    down_shape<TV, TS, TC, CP, TZ, DNWS, DRWS>(tt, tscale, xx, cc, to, kk, g, gc, c, cp, st);
 }
 
 template <typename TV, typename TS, typename TC>
 void down_t(const void* t, const double* tscale, void* x, void* tc, void* tout, const void* kap, Geom g, Geom gc,
             const MGCoef& c, const Couple& cp, hipStream_t st) {
-  if (cp.nz > 0)
-    down_launch<TV, TS, TC, true>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c, cp, st);
+  if (cp.nz > 0 && cp.z_f32)
+    down_launch<TV, TS, TC, true, float>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c,
+                                         cp, st);
+  else if (cp.nz > 0)
+    down_launch<TV, TS, TC, true, double>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c,
+                                          cp, st);
   else
-    down_launch<TV, TS, TC, false>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c, cp, st);
+    down_launch<TV, TS, TC, false, double>((const TV*)t, tscale, (TS*)x, (TS*)tc, (TC*)tout, (const TC*)kap, g, gc, c,
+                                           cp, st);
 }
 
 template <typename TT, typename TS, typename TO, typename TC, int NW, int RW>
@@ -1074,16 +1079,18 @@ void launch_mg_down(int prec, bool t_is_f64, const void* t, const double* tscale
 }
 
 void launch_mg_up(int prec, bool finest, const void* t, const void* x, const void* e, void* out, const void* kappa,
-                  Geom g, Geom gc, const MGCoef& c, hipStream_t st) {
+                  Geom g, Geom gc, const MGCoef& c, hipStream_t st, bool out_f32) {
   if (prec == 0) {
     up_t<double, double, double, double>(t, x, e, out, kappa, g, gc, c, st);
   } else if (prec == 1) {
-    if (finest)
+    if (finest && !out_f32)
       up_t<float, float, double, float>(t, x, e, out, kappa, g, gc, c, st);
     else
       up_t<float, float, float, float>(t, x, e, out, kappa, g, gc, c, st);
   } else {
-    if (finest)
+    if (finest && out_f32)
+      up_t<float, bf16, float, float>(t, x, e, out, kappa, g, gc, c, st);
+    else if (finest)
       up_t<float, bf16, double, float>(t, x, e, out, kappa, g, gc, c, st);
     else
       up_t<bf16, bf16, bf16, float>(t, x, e, out, kappa, g, gc, c, st);
@@ -1091,12 +1098,15 @@ void launch_mg_up(int prec, bool finest, const void* t, const void* x, const voi
 }
 
 void launch_mg_coarse(int prec, bool io_is_f64, const void* t, const double* tscale, void* out, const void* Binv, Geom g,
-                      hipStream_t st) {
+                      hipStream_t st, bool out_f32) {
   const int n = (g.N - 1) * (g.N - 1);
   const dim3 grid((n + NTC / 64 - 1) / (NTC / 64));
   if (prec == 0) {
     launch_k(mg_coarse_kernel<double, double, double>, grid, NTC, st, (const double*)t, tscale, (double*)out,
                                                                  (const double*)Binv, g);
+  } else if (io_is_f64 && out_f32) {
+    launch_k(mg_coarse_kernel<double, float, float>, grid, NTC, st, (const double*)t, tscale, (float*)out,
+                                                               (const float*)Binv, g);
   } else if (io_is_f64) {
     launch_k(mg_coarse_kernel<double, double, float>, grid, NTC, st, (const double*)t, tscale, (double*)out,
                                                                 (const float*)Binv, g);

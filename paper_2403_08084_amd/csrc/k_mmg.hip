@@ -637,22 +637,27 @@ void launch_mmg_down(int prec, bool t_f64, const void* t, const double* tscale, 
 }
 
 void launch_mmg_up(int prec, bool io_f64, const void* t, const double* tscale, const void* x, const void* e, void* out,
-                   const void* kap, Geom g, Geom gc, const MMGCoef& c, hipStream_t st) {
+                   const void* kap, Geom g, Geom gc, const MMGCoef& c, hipStream_t st, bool out_f32) {
   if (prec == 0) up_t<double, double, double, double>(t, tscale, x, e, out, kap, g, gc, c, st);
   else if (prec == 1) {
-    if (io_f64) up_t<double, float, double, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+    if (io_f64 && out_f32) up_t<double, float, float, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+    else if (io_f64) up_t<double, float, double, float>(t, tscale, x, e, out, kap, g, gc, c, st);
     else up_t<float, float, float, float>(t, tscale, x, e, out, kap, g, gc, c, st);
   } else {
-    if (io_f64) up_t<double, bf16, double, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+    if (io_f64 && out_f32) up_t<double, bf16, float, float>(t, tscale, x, e, out, kap, g, gc, c, st);
+    else if (io_f64) up_t<double, bf16, double, float>(t, tscale, x, e, out, kap, g, gc, c, st);
     else up_t<bf16, bf16, bf16, float>(t, tscale, x, e, out, kap, g, gc, c, st);
   }
 }
 
 void launch_mmg_coarse(int prec, bool t_f64, bool out_f64, const void* t, const double* tscale, void* out,
-                       const void* Cinv, Geom g, int s, hipStream_t st) {
+                       const void* Cinv, Geom g, int s, hipStream_t st, bool out_f32) {
   const int n = s * (g.N - 1) * (g.N - 1);
   const dim3 grid((n + 3) / 4), blk(256);
-  if (prec == 0) {
+  if (prec != 0 && t_f64 && out_f32) {
+    launch_k(mmg_coarse_kernel<double, float, float>, grid, blk, st, (const double*)t, tscale, (float*)out,
+                                                                   (const float*)Cinv, g, s);
+  } else if (prec == 0) {
     launch_k(mmg_coarse_kernel<double, double, double>, grid, blk, st, (const double*)t, tscale, (double*)out,
                                                                      (const double*)Cinv, g, s);
   } else if (prec == 1) {

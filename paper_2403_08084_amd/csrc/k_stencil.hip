@@ -22,7 +22,8 @@ struct Nb {
   double c, e, w, n, s, ne, nw, se, sw;
 };
 
-__device__ __forceinline__ Nb load_nb(const double* __restrict__ x, long p, int P) {
+template <typename TX>
+__device__ __forceinline__ Nb load_nb(const TX* __restrict__ x, long p, int P) {
   Nb v;
   v.c = x[p];
   v.e = x[p + 1];
@@ -149,8 +150,8 @@ __global__ void coarsen_kappa_kernel(const double* __restrict__ f, double* __res
 constexpr int RB = 4;
 constexpr int SBY = 4;  // wavefronts per block
 
-template <int S, bool IA>
-__global__ __launch_bounds__(BX* SBY) void stage_operator_kernel(const double* __restrict__ x, double* __restrict__ y,
+template <int S, bool IA, typename TX>
+__global__ __launch_bounds__(BX* SBY) void stage_operator_kernel(const TX* __restrict__ x, double* __restrict__ y,
                                                                 const double* __restrict__ f,
                                                                 const double* __restrict__ kap, Geom g, Coefs a,
                                                                 double dt) {
@@ -178,9 +179,9 @@ __global__ __launch_bounds__(BX* SBY) void stage_operator_kernel(const double* _
     for (int r = 0; r < RB + 2; ++r) {
       const int nr = min(j0 - 1 + r, N);
       const long pr = q * g.plane + (long)nr * P + i;
-      xw[r] = x[pr - 1];
-      xc[r] = x[pr];
-      xe[r] = x[pr + 1];
+      xw[r] = (double)x[pr - 1];
+      xc[r] = (double)x[pr];
+      xe[r] = (double)x[pr + 1];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -258,8 +259,9 @@ __global__ __launch_bounds__(BX* BY) void stiff_kernel(const double* __restrict_
   y[p] = stiff(load_nb(x, p, g.pitch), load_kap(kap, p, g.pitch));
 }
 
+template <typename TZ>
 __global__ __launch_bounds__(BX* BY) void gs_couple_kernel(const double* __restrict__ v, const double* __restrict__ vscale,
-                                                           const double* __restrict__ z, int ns, Coefs row, double dt,
+                                                           const TZ* __restrict__ z, int ns, Coefs row, double dt,
                                                            const double* __restrict__ kap, double* __restrict__ t,
                                                            Geom g, int use_mass, double vmul) {
   int i, j;
@@ -438,24 +440,31 @@ void launch_coarsen_kappa(const double* fine, double* coarse, Geom gf, Geom gc, 
   launch_k(coarsen_kappa_kernel, flat_blocks((long)gc.N * gc.pitch), 256, st, fine, coarse, gf, gc);
 }
 
-template <bool IA>
-void stage_operator_t(const double* x, double* y, const double* f, const double* kappa, Geom g, int s, const Coefs& a,
+template <bool IA, typename TX>
+void stage_operator_t(const TX* x, double* y, const double* f, const double* kappa, Geom g, int s, const Coefs& a,
                       double dt, hipStream_t st) {
   const int ntx = (g.N - 1 + BX - 1) / BX, nty = (g.N - 1 + SBY * RB - 1) / (SBY * RB);
   const dim3 grid(ntx * nty), blk(BX, SBY);
   switch (s) {
-    case 1: launch_k(stage_operator_kernel<1, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    case 2: launch_k(stage_operator_kernel<2, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    case 3: launch_k(stage_operator_kernel<3, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    case 4: launch_k(stage_operator_kernel<4, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    case 5: launch_k(stage_operator_kernel<5, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    case 6: launch_k(stage_operator_kernel<6, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    case 7: launch_k(stage_operator_kernel<7, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
-    default: launch_k(stage_operator_kernel<8, IA>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 1: launch_k(stage_operator_kernel<1, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 2: launch_k(stage_operator_kernel<2, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 3: launch_k(stage_operator_kernel<3, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 4: launch_k(stage_operator_kernel<4, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 5: launch_k(stage_operator_kernel<5, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 6: launch_k(stage_operator_kernel<6, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    case 7: launch_k(stage_operator_kernel<7, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
+    default: launch_k(stage_operator_kernel<8, IA, TX>, grid, blk, st, x, y, f, kappa, g, a, dt); break;
   }
 }
 
 void launch_stage_operator(const double* x, double* y, const double* f, const double* kappa, Geom g, int s,
+                           const Coefs& a, double dt, hipStream_t st, bool ia) {
+  if (ia)
+    stage_operator_t<true>(x, y, f, kappa, g, s, a, dt, st);
+  else
+    stage_operator_t<false>(x, y, f, kappa, g, s, a, dt, st);
+}
+void launch_stage_operator(const float* x, double* y, const double* f, const double* kappa, Geom g, int s,
                            const Coefs& a, double dt, hipStream_t st, bool ia) {
   if (ia)
     stage_operator_t<true>(x, y, f, kappa, g, s, a, dt, st);
@@ -474,7 +483,13 @@ void launch_stiff(const double* x, double* y, const double* kappa, Geom g, hipSt
 }
 void launch_gs_couple(const double* v, const double* vscale, const double* z, int nz, const Coefs& row, double dt,
                       const double* kappa, double* t, Geom g, hipStream_t st, int mass, double vmul) {
-  launch_k(gs_couple_kernel, stencil_grid(g), dim3(BX, BY), st, v, vscale, z, nz, row, dt, kappa, t, g, mass, vmul);
+  launch_k(gs_couple_kernel<double>, stencil_grid(g), dim3(BX, BY), st, v, vscale, z, nz, row, dt, kappa, t, g, mass,
+           vmul);
+}
+void launch_gs_couple(const double* v, const double* vscale, const float* z, int nz, const Coefs& row, double dt,
+                      const double* kappa, double* t, Geom g, hipStream_t st, int mass, double vmul) {
+  launch_k(gs_couple_kernel<float>, stencil_grid(g), dim3(BX, BY), st, v, vscale, z, nz, row, dt, kappa, t, g, mass,
+           vmul);
 }
 void launch_update(double* u, const double* k, int s, const Coefs& b, double dt, Geom g, hipStream_t st) {
   launch_k(update_kernel, flat_blocks(g.plane), 256, st, u, k, s, b, dt, g.plane);

@@ -163,6 +163,10 @@ struct irk_stepper {
   // set by the time step when its right-hand side kernel also wrote f into V_0: the next DCGS2 solve of st->f
   // without a guess then needs no copy (cleared by every solve)
   bool v0_is_f = false;
+  // the mixed form keeps its flexible basis Z in FP32: the preconditioner's output is computed in FP32, so the
+  // stored values are the same, at half the bytes for the finest UP, the operator, the stage coupling and the
+  // solution update
+  bool zf32 = false;
   int sys = -1;       // system the Krylov solver works on: -1 the coupled one, i >= 0 DIRK stage i
   // adjoint workspace, allocated by the first irk_adjoint call: checkpoint planes (grown when a call needs
   // more slots), the adjoint state, the padded gradient and two stage vectors
@@ -263,16 +267,17 @@ struct Bytes {
 };
 double compute_bytes(const irk_stepper* st) { return st->prec == 0 ? 8.0 : 4.0; }
 
-// single-stage DOWN on level l (nz coupled FP64 stage planes read at the finest level)
-Bytes mg_down_bytes(const irk_stepper* st, int l, int nz) {
+// single-stage DOWN on level l (nz coupled stage planes of zb bytes a value read at the finest level)
+Bytes mg_down_bytes(const irk_stepper* st, int l, int nz, double zb = 8.0) {
   const double n = nodes(st->lv[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st);
   const double tin = l == 0 ? 8.0 : p, tout = l == 0 ? c : 0.0;
-  return {n * (8.25 * p + 2 * c + 8.0 * nz), n * (tin + c + p + 0.25 * p + tout + 8.0 * nz)};
+  return {n * (8.25 * p + 2 * c + zb * nz), n * (tin + c + p + 0.25 * p + tout + zb * nz)};
 }
 
-Bytes mg_up_bytes(const irk_stepper* st, int l) {
+// single-stage UP on level l (the finest writes ob bytes a value)
+Bytes mg_up_bytes(const irk_stepper* st, int l, double ob = 8.0) {
   const double n = nodes(st->lv[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st);
-  const double tin = l == 0 ? c : p, out = l == 0 ? 8.0 : p;
+  const double tin = l == 0 ? c : p, out = l == 0 ? ob : p;
   return {n * (8.25 * p + 2 * c), n * (tin + p + 0.25 * p + c + out)};
 }
 
@@ -303,9 +308,10 @@ Bytes mg_up3_bytes(const irk_stepper* st, int a) {
   return b;
 }
 
-// dense coarsest solve on nv unknowns: the inverse once, the right-hand side and the result
-Bytes coarse_bytes(const irk_stepper* st, double nv, bool io64) {
-  const double c = compute_bytes(st), io = io64 ? 16.0 : 2.0 * (double)storage_bytes(st->prec);
+// dense coarsest solve on nv unknowns: the inverse once, the right-hand side and the result (io64: an FP64
+// right-hand side and a result of ob bytes a value)
+Bytes coarse_bytes(const irk_stepper* st, double nv, bool io64, double ob = 8.0) {
+  const double c = compute_bytes(st), io = io64 ? 8.0 + ob : 2.0 * (double)storage_bytes(st->prec);
   const double b = nv * nv * c + nv * io;
   return {b, b};
 }
@@ -317,10 +323,10 @@ Bytes mmg_down_bytes(const irk_stepper* st, int l) {
   return {n * (s * 8.25 * p + 2 * c), n * (s * tin + c + s * p + s * 0.25 * p)};
 }
 
-Bytes mmg_up_bytes(const irk_stepper* st, int l) {
+Bytes mmg_up_bytes(const irk_stepper* st, int l, double ob = 8.0) {
   const double n = nodes(st->ml[l].g), p = (double)storage_bytes(st->prec), c = compute_bytes(st), s = st->s;
-  const double io = l == 0 ? 8.0 : p;
-  return {n * (s * 8.25 * p + 2 * c), n * (s * io + s * p + s * 0.25 * p + c + s * io)};
+  const double io = l == 0 ? 8.0 : p, out = l == 0 ? ob : p;
+  return {n * (s * 8.25 * p + 2 * c), n * (s * io + s * p + s * 0.25 * p + c + s * out)};
 }
 
 int arm(irk_stepper* st, int family, const Bytes& b) { return timer_arm(st, family, b.model, b.min); }
@@ -331,7 +337,7 @@ double ortho_bytes(const irk_stepper* st, const OrthoArgs& a) {
   const double vec = 8.0 * (double)(a.len / st->g.plane) * (double)(st->prob->N - 1) * (st->prob->N - 1);
   const bool ax = a.coef != nullptr, dt = a.want_dots != 0;
   const int nvec = (a.nv > 0 && (ax || dt)) ? a.nv : 0;
-  return vec * (nvec + ((ax && a.assign) ? 0 : 1) + (ax ? 1 : 0));
+  return vec * ((a.Vf ? 0.5 : 1.0) * nvec + ((ax && a.assign) ? 0 : 1) + (ax ? 1 : 0));
 }
 
 // Algorithmic bytes of the two DCGS2 passes over nv finished vectors: the reduction reads Q, u and w;
@@ -342,6 +348,7 @@ double dcgs2_bytes(const irk_stepper* st, int nv, long len, bool update) {
 }
 
 int ortho(irk_stepper* st, const OrthoArgs& a, hipStream_t s) {
+  if (a.Vf && (a.coef == nullptr || a.want_dots)) return fail(IRK_EINVAL, "an FP32 basis is read by update passes only");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // only passes over the Krylov vectors are timed (not the setup's per-level norms); with DCGS2 the timed
   // family is its reduction and update passes alone
@@ -694,7 +701,8 @@ int setup_mmg(irk_stepper* st, hipStream_t s) {
 
 // out = one monolithic V-cycle for the coupled system (forward or transposed) applied to tscale * t
 // (FP64 padded stage blocks)
-int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, double* out, bool trans, hipStream_t s) {
+int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, void* out, bool out_f32, bool trans,
+               hipStream_t s) {
   std::vector<Level>& ml = st->ml;
   const int L = (int)ml.size();
   const int pr = st->prec, ns = st->s;
@@ -702,8 +710,8 @@ int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, double* o
   const void* cinv = st->mcinv[trans ? 1 : 0];
   const double nc = (double)ns * nodes(ml[L - 1].g);
   if (L == 1) {
-    CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nc, true)));
-    launch_mmg_coarse(pr, true, true, t, tscale, out, cinv, ml[0].g, ns, s);
+    CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nc, true, out_f32 ? 4.0 : 8.0)));
+    launch_mmg_coarse(pr, true, true, t, tscale, out, cinv, ml[0].g, ns, s, out_f32);
     return check_launch();
   }
   for (int l = 0; l < L - 1; ++l) {
@@ -714,17 +722,17 @@ int mmg_vcycle(irk_stepper* st, const double* t, const double* tscale, double* o
   CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nc, false)));
   launch_mmg_coarse(pr, false, false, ml[L - 1].t, nullptr, ml[L - 1].e, cinv, ml[L - 1].g, ns, s);
   for (int l = L - 2; l >= 0; --l) {
-    CHK(arm(st, l == 0 ? IRK_KFAM_MG_FINE : IRK_KFAM_MG_COARSE, mmg_up_bytes(st, l)));
+    CHK(arm(st, l == 0 ? IRK_KFAM_MG_FINE : IRK_KFAM_MG_COARSE, mmg_up_bytes(st, l, out_f32 ? 4.0 : 8.0)));
     launch_mmg_up(pr, l == 0, l == 0 ? (const void*)t : ml[l].t, l == 0 ? tscale : nullptr, ml[l].x, ml[l + 1].e,
-                  l == 0 ? (void*)out : ml[l].e, ml[l].kapc, ml[l].g, ml[l + 1].g, cf[l], s);
+                  l == 0 ? out : ml[l].e, ml[l].kapc, ml[l].g, ml[l + 1].g, cf[l], s, l == 0 && out_f32);
   }
   return check_launch();
 }
 
 // ------------------------------------------------------------------ preconditioner
 
-// out = one V-cycle for block `stage` applied to tscale * t (FP64 padded planes)
-int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, double* out, hipStream_t s,
+// out = one V-cycle for block `stage` applied to tscale * t (FP64 padded planes; out FP32 with out_f32)
+int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, void* out, bool out_f32, hipStream_t s,
            const Couple* cpl = nullptr) {
   const int L = (int)st->lv.size();
   Couple none{};
@@ -732,8 +740,8 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
   const MGCoef* cf = &st->coef[(size_t)stage * L];
   const int pr = st->prec;
   if (L == 1) {
-    CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nodes(st->lv[0].g), true)));
-    launch_mg_coarse(pr, true, t, tscale, out, st->binv[stage], st->lv[0].g, s);
+    CHK(arm(st, IRK_KFAM_COARSE_SOLVE, coarse_bytes(st, nodes(st->lv[0].g), true, out_f32 ? 4.0 : 8.0)));
+    launch_mg_coarse(pr, true, t, tscale, out, st->binv[stage], st->lv[0].g, s, out_f32);
     return check_launch();
   }
   std::vector<Level>& lv = st->lv;
@@ -755,7 +763,7 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
     }
   }
   // the finest DOWN stores the right-hand side it smoothed (scaled, with the stage coupling) for the finest UP
-  CHK(arm(st, IRK_KFAM_MG_FINE, mg_down_bytes(st, 0, cp.nz)));
+  CHK(arm(st, IRK_KFAM_MG_FINE, mg_down_bytes(st, 0, cp.nz, cp.z_f32 ? 4.0 : 8.0)));
   launch_mg_down(pr, true, t, tscale, lv[0].x, lv[1].t, lv[0].tp, lv[0].kapc, lv[0].g, lv[1].g, cf[0], cp, s);
   for (int l = 1; l < (three ? A3 : L - 1); ++l) {
     CHK(arm(st, IRK_KFAM_MG_COARSE, mg_down_bytes(st, l, 0)));
@@ -776,8 +784,8 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
     CHK(arm(st, IRK_KFAM_MG_COARSE, mg_up_bytes(st, l)));
     launch_mg_up(pr, false, lv[l].t, lv[l].x, lv[l + 1].e, lv[l].e, lv[l].kapc, lv[l].g, lv[l + 1].g, cf[l], s);
   }
-  CHK(arm(st, IRK_KFAM_MG_FINE, mg_up_bytes(st, 0)));
-  launch_mg_up(pr, true, lv[0].tp, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s);
+  CHK(arm(st, IRK_KFAM_MG_FINE, mg_up_bytes(st, 0, out_f32 ? 4.0 : 8.0)));
+  launch_mg_up(pr, true, lv[0].tp, lv[0].x, lv[1].e, out, lv[0].kapc, lv[0].g, lv[1].g, cf[0], s, out_f32);
   return check_launch();
 }
 
@@ -785,10 +793,15 @@ int vcycle(irk_stepper* st, int stage, const double* t, const double* tscale, do
 // AI form: P = I (x) M + dt Atil (x) K, z_i = B_i^{-1} (v_i - dt K sum_j atil_ij z_j).
 // IA form: P = Atil^{-1} (x) M + dt I (x) K, z_i = atil_ii B_i^{-1} (v_i - M sum_j c_ij z_j) with
 // C = Atil^{-1}, B_i = M + dt atil_ii K (one V-cycle is linear, so atil_ii scales its input).
-int precondition(irk_stepper* st, const double* v, const double* vscale, double* z, bool trans, hipStream_t s) {
-  if (st->sys >= 0) return vcycle(st, st->sys, v, vscale, z, s);  // one DIRK stage: one V-cycle
-  if (st->opt.precond == IRK_PC_MONOLITHIC) return mmg_vcycle(st, v, vscale, z, trans, s);
+// z: FP64 planes, or FP32 planes with zf (the stage coupling then reads them as FP32)
+int precondition(irk_stepper* st, const double* v, const double* vscale, void* z, bool zf, bool trans, hipStream_t s) {
+  if (st->sys >= 0) return vcycle(st, st->sys, v, vscale, z, zf, s);  // one DIRK stage: one V-cycle
+  if (st->opt.precond == IRK_PC_MONOLITHIC) return mmg_vcycle(st, v, vscale, z, zf, trans, s);
   const long plane = st->g.plane;
+  // stage plane q of z
+  auto zplane = [&](int q) -> void* {
+    return zf ? (void*)((float*)z + (long)q * plane) : (void*)((double*)z + (long)q * plane);
+  };
   const int ns = st->s;
   const Coefs a = ptil_of(st, trans);
   const double* Ci = st->Ci[trans ? 1 : 0];
@@ -802,7 +815,7 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
     const int nc = (st->opt.precond == IRK_PC_JACOBI) ? 0 : step;
     const double vmul = st->ia ? st->pd[i] : 1.0;
     const double* vi = v + i * plane;
-    double* zi = z + i * plane;
+    void* zi = zplane(i);
     double row[kMaxStages] = {};
     for (int q = 0; q < nc; ++q)
       row[q] = st->ia ? vmul * Ci[i * ns + j0 + q] : a.a[i * kMaxStages + j0 + q];
@@ -810,7 +823,8 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
       if (st->lv.size() > 1) {
         // the coupling and the scale are applied inside the finest-level kernels
         Couple cp{};
-        cp.z = z + j0 * plane;
+        cp.z = zplane(j0);
+        cp.z_f32 = zf ? 1 : 0;
         cp.zstride = plane;
         cp.nz = nc;
         cp.mass = st->ia ? 1 : 0;
@@ -818,36 +832,42 @@ int precondition(irk_stepper* st, const double* v, const double* vscale, double*
         cp.mh = st->g.h * st->g.h / 36.0;
         cp.vmul = vmul;
         for (int q = 0; q < nc; ++q) cp.a[q] = row[q];
-        CHK(vcycle(st, i, vi, vscale, zi, s, &cp));
+        CHK(vcycle(st, i, vi, vscale, zi, zf, s, &cp));
       } else {
         Coefs r{};
         for (int q = 0; q < nc; ++q) r.a[q] = row[q];
         double* t = st->tmp2;
-        const double gb = nodes(st->g) * (24.0 + 8.0 * nc);
+        const double gb = nodes(st->g) * (24.0 + (zf ? 4.0 : 8.0) * nc);
         CHK(timer_arm(st, IRK_KFAM_OTHER, gb, gb));
-        launch_gs_couple(vi, vscale, z + j0 * plane, nc, r, st->ia ? 1.0 : st->dt, st->prob->kappa, t, st->g, s,
-                         st->ia ? 1 : 0, vmul);
-        CHK(vcycle(st, i, t, nullptr, zi, s));
+        if (zf)
+          launch_gs_couple(vi, vscale, (const float*)zplane(j0), nc, r, st->ia ? 1.0 : st->dt, st->prob->kappa, t,
+                           st->g, s, st->ia ? 1 : 0, vmul);
+        else
+          launch_gs_couple(vi, vscale, (const double*)zplane(j0), nc, r, st->ia ? 1.0 : st->dt, st->prob->kappa, t,
+                           st->g, s, st->ia ? 1 : 0, vmul);
+        CHK(vcycle(st, i, t, nullptr, zi, zf, s));
       }
     } else {
-      CHK(vcycle(st, i, vi, vscale, zi, s));
+      CHK(vcycle(st, i, vi, vscale, zi, zf, s));
     }
   }
   return check_launch();
 }
 
-int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s) {
+// y = Acal x (y = f - Acal x with f); xf: x is FP32 (a vector of the mixed form's flexible basis) at xf instead
+int apply_op(irk_stepper* st, const double* x, double* y, const double* f, bool trans, hipStream_t s,
+             const float* xf = nullptr) {
   const int ns = st->sys >= 0 ? 1 : st->s;
-  const double ob = nodes(st->g) * (16.0 * ns + 8.0 + (f ? 8.0 * ns : 0.0));
+  const double ob = nodes(st->g) * ((xf ? 4.0 : 8.0) * ns + 8.0 * ns + 8.0 + (f ? 8.0 * ns : 0.0));
   CHK(timer_arm(st, IRK_KFAM_OPERATOR, ob, ob));
-  if (st->sys >= 0) {
-    // one DIRK stage: M + dt a_ii K (symmetric)
-    Coefs a{};
-    a.a[0] = st->A[st->sys * st->s + st->sys];
-    launch_stage_operator(x, y, f, st->prob->kappa, st->g, 1, a, st->dt, s);
-    return check_launch();
-  }
-  launch_stage_operator(x, y, f, st->prob->kappa, st->g, st->s, coefs_of(st, trans), st->dt, s, st->ia);
+  Coefs a{};
+  if (st->sys >= 0) a.a[0] = st->A[st->sys * st->s + st->sys];  // one DIRK stage: M + dt a_ii K (symmetric)
+  const Coefs& c = st->sys >= 0 ? a : coefs_of(st, trans);
+  const bool ia = st->sys < 0 && st->ia;
+  if (xf)
+    launch_stage_operator(xf, y, f, st->prob->kappa, st->g, ns, c, st->dt, s, ia);
+  else
+    launch_stage_operator(x, y, f, st->prob->kappa, st->g, ns, c, st->dt, s, ia);
   return check_launch();
 }
 
@@ -866,8 +886,8 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
   if (st->opt.orth == IRK_ORTH_DCGS2) {
     // Z_j = P^{-1} u_j (u_j = V_j: the previous direction, projected once), w = Acal Z_j into V_{j+1},
     // then one reduction and one update pass: V_j <- q_j, V_{j+1} <- the next direction
-    CHK(precondition(st, Vj, nullptr, Zj, trans, s));
-    CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
+    CHK(precondition(st, Vj, nullptr, Zj, st->zf32, trans, s));
+    CHK(apply_op(st, Zj, Vn, nullptr, trans, s, st->zf32 ? (const float*)Zj : nullptr));
     D2Args d{st->V, n, j, Vj, Vn, n, dcgs2_dev(st, j & 1), st->hmir_dev + (long)(j & 1) * kDcgs2Res};
     hipEvent_t e0, e1, e2, e3;
     const double b0 = dcgs2_bytes(st, j, n, false), b1 = dcgs2_bytes(st, j, n, true);
@@ -878,8 +898,8 @@ int arnoldi_body(irk_stepper* st, int j, bool trans, hipStream_t s) {
     launch_dcgs2_update(d, st->rw, s, e2, e3);
     return check_launch();
   }
-  CHK(precondition(st, Vj, sig + j, Zj, trans, s));
-  CHK(apply_op(st, Zj, Vn, nullptr, trans, s));
+  CHK(precondition(st, Vj, sig + j, Zj, st->zf32, trans, s));
+  CHK(apply_op(st, Zj, Vn, nullptr, trans, s, st->zf32 ? (const float*)Zj : nullptr));
   // pass A: h = V^T w, |w|^2
   OrthoArgs a = ortho_base();
   a.V = st->V;
@@ -944,6 +964,19 @@ struct SolveInfo {
   int solves = 0, its_max = 0;
   int discarded = 0;  // Arnoldi steps launched ahead of the host's decision and not used
 };
+
+// the flexible basis as the basis of an update pass (x = Z y): Z_j starts n FP64 values after Z_{j-1}, so an FP32
+// basis has a stride of 2n values
+void set_z_basis(const irk_stepper* st, OrthoArgs& a, long n) {
+  if (st->zf32) {
+    a.V = nullptr;
+    a.Vf = (const float*)st->Z;
+    a.vstride = 2 * n;
+  } else {
+    a.V = st->Z;
+    a.vstride = n;
+  }
+}
 
 // FGMRES with the delayed CGS2 Arnoldi process. The Hessenberg column of step j is provisional until
 // step j+1 re-orthogonalises and normalises the direction it produced: then the column gains the
@@ -1069,8 +1102,7 @@ int fgmres_dcgs2(irk_stepper* st, const double* f, bool trans, bool use_guess, S
       std::copy(y.begin(), y.begin() + jdone, h);
       HIPCHK(hipMemcpyAsync(ycoef_dev(st), h, jdone * sizeof(double), hipMemcpyHostToDevice, s));
       OrthoArgs ax = ortho_base();
-      ax.V = st->Z;
-      ax.vstride = n;
+      set_z_basis(st, ax, n);
       ax.nv = jdone;
       ax.w = x;
       ax.len = n;
@@ -1203,8 +1235,7 @@ int fgmres(irk_stepper* st, const double* f, bool trans, bool use_guess, SolveIn
     HIPCHK(hipMemcpyAsync(ycoef_dev(st), h, jdone * sizeof(double), hipMemcpyHostToDevice, s));
     {
       OrthoArgs a = ortho_base();
-      a.V = st->Z;
-      a.vstride = n;
+      set_z_basis(st, a, n);
       a.nv = jdone;
       a.w = x;
       a.len = n;
@@ -1698,6 +1729,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
         }
   }
   st->prec = o.mg_precision;
+  st->zf32 = st->prec != 0;
   st->g = p->g;
   st->vlen = (long)s * p->g.plane;
   hipStream_t hs = S(stream);
@@ -1833,7 +1865,7 @@ int irk_apply_preconditioner(const irk_stepper* cst, const double* v, double* z,
   irk_stepper* st = const_cast<irk_stepper*>(cst);
   hipStream_t s = S(stream);
   launch_pack(v, st->f, st->g, st->s, s);
-  CHK(precondition(st, st->f, nullptr, st->k, transpose != 0, s));
+  CHK(precondition(st, st->f, nullptr, st->k, false, transpose != 0, s));
   launch_unpack(st->k, z, st->g, st->s, s);
   return check_launch();
 }
@@ -1846,7 +1878,7 @@ int irk_vcycle(const irk_stepper* cst, int stage, const double* t, double* z, vo
   irk_stepper* st = const_cast<irk_stepper*>(cst);
   hipStream_t s = S(stream);
   launch_pack(t, st->f, st->g, 1, s);
-  CHK(vcycle(st, stage, st->f, nullptr, st->k, s));
+  CHK(vcycle(st, stage, st->f, nullptr, st->k, false, s));
   launch_unpack(st->k, z, st->g, 1, s);
   return check_launch();
 }

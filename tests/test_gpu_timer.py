@@ -36,12 +36,14 @@ def test_timer_accounts_every_family(prec):
         assert bmin <= by + 1e-6
     # one finest DOWN and one finest UP per stage V-cycle, s V-cycles per preconditioner application
     assert fam[P.KFAM_MG_FINE][0] == 2 * s * cycles
-    # the stage operator's bytes: the s input planes and s output planes in FP64 and the FP64 diffusivity, plus the
-    # right-hand side's s planes for the true-residual check that ends every restart cycle of every solve
+    # the stage operator's bytes: the s input planes (vectors of the flexible basis: FP32 in the mixed form, FP64
+    # otherwise), s FP64 output planes and the FP64 diffusivity; the true-residual check that ends every restart
+    # cycle of every solve reads an FP64 input and the right-hand side's s planes besides
     launches, _, by, _ = fam[P.KFAM_OPERATOR]
     residuals = st["solves"] + st["restarts_total"]
     assert launches == cycles + residuals
-    assert by == pytest.approx((launches * (16 * s + 8) + residuals * 8 * s) * n, rel=1e-12)
+    zb = 4 if prec != P.F64 else 8
+    assert by == pytest.approx((cycles * (zb * s + 8 * s + 8) + residuals * (24 * s + 8)) * n, rel=1e-12)
     # the aggregate is the sum of the families
     tot = stp.kernel_timer_family(P.KFAM_ALL)
     assert tot[0] == sum(v[0] for v in fam.values())
