@@ -108,7 +108,9 @@ typedef struct {
   double cheb_lo;     /* smoothing interval [cheb_lo*mu, cheb_hi*mu]              */
   double cheb_hi;
   int power_its;      /* power iterations for the largest eigenvalue mu            */
-  int mg_precision;   /* IRK_F64, IRK_F32 or IRK_BF16 (storage; BF16 computes in FP32) */
+  int mg_precision;   /* IRK_F64, IRK_F32 or IRK_BF16 (storage; BF16 computes in FP32). With IRK_F32 or
+                         IRK_BF16 the flexible basis of preconditioned vectors is kept in FP32 (the values
+                         the FP32 multigrid computed); the Krylov basis, residuals and updates stay FP64 */
   int orth;           /* IRK_ORTH_DCGS2 (default), IRK_ORTH_CGS2 or IRK_ORTH_CGS_SELECTIVE */
   int initial_guess;  /* IRK_GUESS_ZERO or IRK_GUESS_PREV (previous step's k)     */
   int use_graphs;     /* 1: replay each Krylov iteration as a captured HIP graph;  
