@@ -118,6 +118,8 @@ typedef struct {
   int splitting;      /* IRK_SPLIT_AI (default) or IRK_SPLIT_IA                    */
   int stage_type;     /* IRK_STAGE_COUPLED (default) or IRK_STAGE_DIRK             */
   int lookahead;      /* IRK_LOOKAHEAD_ADAPTIVE (default), IRK_LOOKAHEAD_OFF or IRK_LOOKAHEAD_ALWAYS */
+  int basis_f64;      /* 1: keep the flexible basis in FP64 with IRK_F32 / IRK_BF16 as well (the same
+                         values, twice the bytes: a check of the FP32 basis); 0 (default) */
 } irk_options;
 
 /* Per-call statistics (host struct, filled if non-NULL). */

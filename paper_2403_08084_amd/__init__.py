@@ -15,7 +15,8 @@ Stepper options (fields of irk_options; defaults from irk_options_default):
   precond       PC_GS_LOWER (block lower Gauss-Seidel), PC_JACOBI, PC_GS_UPPER, PC_RANA_LD, PC_MONOLITHIC
   splitting     SPLIT_AI (stage derivatives k) or SPLIT_IA (w = (A (x) I) k)
   stage_type    STAGE_COUPLED or STAGE_DIRK (stage-by-stage solves, lower-triangular A)
-  mg_precision  F64, F32 or BF16 storage of the multigrid vectors (FGMRES stays FP64)
+  mg_precision  F64, F32 or BF16 storage of the multigrid vectors (FGMRES stays FP64; with F32 / BF16 the
+                flexible basis of preconditioned vectors is FP32 unless basis_f64=1, which gives the same bits)
   orth          ORTH_DCGS2 (one reduction per Arnoldi step), ORTH_CGS2, ORTH_CGS_SELECTIVE
   lookahead     LOOKAHEAD_ADAPTIVE (queue the next Arnoldi step before the host's convergence test
                 while the residual history predicts it is needed), LOOKAHEAD_OFF, LOOKAHEAD_ALWAYS
@@ -77,6 +78,7 @@ class Options(ctypes.Structure):
         ("splitting", ctypes.c_int),
         ("stage_type", ctypes.c_int),
         ("lookahead", ctypes.c_int),
+        ("basis_f64", ctypes.c_int),
     ]
 
 

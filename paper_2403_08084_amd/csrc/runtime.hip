@@ -1481,6 +1481,7 @@ void irk_options_default(irk_options* o) {
   o->splitting = IRK_SPLIT_AI;
   o->stage_type = IRK_STAGE_COUPLED;
   o->lookahead = IRK_LOOKAHEAD_ADAPTIVE;
+  o->basis_f64 = 0;
 }
 
 int irk_problem_create(irk_problem** out, int N, const double* kappa, void* stream) {
@@ -1636,6 +1637,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
   if (o.splitting != IRK_SPLIT_AI && o.splitting != IRK_SPLIT_IA) return fail(IRK_EINVAL, "unknown splitting");
   if (o.stage_type != IRK_STAGE_COUPLED && o.stage_type != IRK_STAGE_DIRK) return fail(IRK_EINVAL, "unknown stage_type");
   if (o.lookahead < IRK_LOOKAHEAD_OFF || o.lookahead > IRK_LOOKAHEAD_ALWAYS) return fail(IRK_EINVAL, "unknown lookahead");
+  if (o.basis_f64 != 0 && o.basis_f64 != 1) return fail(IRK_EINVAL, "basis_f64 must be 0 or 1");
   if (o.stage_type == IRK_STAGE_DIRK) {
     if (o.splitting != IRK_SPLIT_AI) return fail(IRK_EINVAL, "the DIRK stage type solves the AI form");
     for (int i = 0; i < tab->s; ++i)
@@ -1729,7 +1731,7 @@ int irk_stepper_create(irk_stepper** out, const irk_problem* p, const irk_tablea
         }
   }
   st->prec = o.mg_precision;
-  st->zf32 = st->prec != 0;
+  st->zf32 = st->prec != 0 && o.basis_f64 == 0;
   st->g = p->g;
   st->vlen = (long)s * p->g.plane;
   hipStream_t hs = S(stream);

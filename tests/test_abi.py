@@ -34,7 +34,7 @@ def test_options_default():
     assert o.orth == P.ORTH_DCGS2 and o.splitting == P.SPLIT_AI and o.stage_type == P.STAGE_COUPLED
     assert o.lookahead == P.LOOKAHEAD_ADAPTIVE
     assert o.cheb_degree == 2 and o.cheb_lo == 0.25 and o.cheb_hi == 1.1
-    assert o.mg_precision == P.F64 and o.use_graphs == 1
+    assert o.mg_precision == P.F64 and o.use_graphs == 1 and o.basis_f64 == 0
     with pytest.raises(TypeError):
         P.default_options(nonsense=1)
 

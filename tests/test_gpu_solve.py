@@ -497,3 +497,33 @@ def test_lookahead_rejects_unknown_mode():
     kap = synth.grf_kappa(16, 1)
     with pytest.raises(P.IrkError):
         make(16, kap, P.tableaux.radau_iia(2), 1e-3, lookahead=3)
+
+
+@pytest.mark.parametrize("N,prec,pc,split,orth,stage", [
+    (128, P.F32, P.PC_GS_LOWER, P.SPLIT_AI, P.ORTH_DCGS2, P.STAGE_COUPLED),
+    (128, P.BF16, P.PC_RANA_LD, P.SPLIT_IA, P.ORTH_DCGS2, P.STAGE_COUPLED),
+    (128, P.F32, P.PC_MONOLITHIC, P.SPLIT_AI, P.ORTH_CGS2, P.STAGE_COUPLED),
+    (128, P.F32, P.PC_GS_LOWER, P.SPLIT_AI, P.ORTH_DCGS2, P.STAGE_DIRK),
+    (33, P.F32, P.PC_GS_UPPER, P.SPLIT_AI, P.ORTH_DCGS2, P.STAGE_COUPLED),
+    (512, P.F32, P.PC_GS_LOWER, P.SPLIT_AI, P.ORTH_DCGS2, P.STAGE_COUPLED)])
+def test_fp32_flexible_basis_gives_the_fp64_basis_bits(N, prec, pc, split, orth, stage):
+    # the mixed form keeps the preconditioned vectors Z_j in FP32; the FP32 multigrid computed them, so the
+    # stored values are those an FP64 basis holds: steps, transposed stage solves and the adjoint agree bit for bit
+    kap = synth.grf_kappa(N, 1)
+    tab = P.tableaux.alexander() if stage == P.STAGE_DIRK else P.tableaux.radau_iia(3)
+    opts = dict(mg_precision=prec, precond=pc, splitting=split, orth=orth, stage_type=stage, rtol=1e-10)
+    res = []
+    for basis_f64 in (0, 1):
+        _, stp = make(N, kap, tab, 1e-3, basis_f64=basis_f64, **opts)
+        u = dev(synth.sine_modes_u0(N, 0)[0])
+        _, st = stp.advance(u, 3)
+        k, stt = stp.solve_stages(dev(synth.random_stage_block(N, 3, 4).ravel()), transpose=True)
+        out = [host(u), host(k), st["fgmres_its_total"], stt["fgmres_its_total"]]
+        if N == 128 and pc == P.PC_GS_LOWER and stage == P.STAGE_COUPLED:
+            lam0, grad, _ = stp.adjoint(dev(synth.sine_modes_u0(N, 0)[0]), 4, 2, dev(synth.sine_modes_u0(N, 1)[0]))
+            out += [host(lam0), host(grad)]
+        res.append(out)
+    for a, b in zip(*res):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    with pytest.raises(P.IrkError):
+        make(16, synth.grf_kappa(16, 1), P.tableaux.radau_iia(3), 1e-3, basis_f64=2)
