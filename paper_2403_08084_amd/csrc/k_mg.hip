@@ -26,7 +26,9 @@
 //
 // Storage type TS (FP64, FP32 or BF16) holds the level vectors; arithmetic and
 // kappa use TC (FP64, or FP32 for both reduced-precision forms). TV is the type
-// of the finest level's right-hand side and result (the FP64 Krylov vectors).
+// of the finest level's right-hand side (the FP64 Krylov vector); the finest
+// result TO is FP64, or FP32 for the reduced-precision forms' flexible basis
+// (it holds the TC values either way), and TZ the type of the coupled stages.
 #include "mg_device.h"
 
 namespace irk {
